@@ -1,0 +1,217 @@
+/*
+ * satsplat.h — C ABI of the MI355X (gfx950) hot path of SatSplat (arXiv 2606.28581):
+ * the differentiable 2D-Gaussian-surfel rasterizer under affine satellite cameras
+ * (forward and backward) and the geometric sun-view shadow-map pass.
+ *
+ * Paper passages implemented (section / equation of the paper):
+ *   surfels                 Sec. 3.1 "2D Gaussian Splatting", Eqs. (2dgs_splat_param), (2dgs_splat_H)
+ *   affine camera           Sec. 3.1 Eq. (affine_camera); Sec. 3.2 Eq. (decompose_affine_camera)
+ *   ray-splat intersection  Sec. 3.2 Eqs. (affine2dgs_uv2screen), (affine2dgs_screen2uv), (affine2dgs_Qq)
+ *   depth / sort key        Sec. 3.2 Eq. (depth_affine_camera), "Rasterization"
+ *   low-pass floor          Sec. 3.2 "Degenerate Solutions"
+ *   normal                  Sec. 3.2 "Normal Definition"
+ *   compositing             Sec. 3.2 Eq. (rasterization), 16x16 tiles by default
+ *   image formation         Sec. 3.1 Eq. (image_formation)
+ *   camera delta            Sec. 3.3: F'_xy = F_xy + dF_xy, dF_xy a 2x4 matrix
+ *   sun camera              Sec. 3.3 Eq. (sun_camera_Bxy); Supp. A
+ *   soft shadow test        Sec. 3.1 (exponential-shadow-map filtering of the sun test)
+ *
+ * Conventions
+ *   - Every call returns ss_status: SS_OK (0) or a negative error code.  No call aborts,
+ *     no C++ exception crosses the ABI.  ss_last_error() gives a thread-local message.
+ *   - Tensors are caller-owned DEVICE memory unless marked "host".  The library never
+ *     frees caller memory.  Scratch memory is one caller-provided workspace per plan
+ *     (size from ss_plan_workspace_size); the library itself allocates no device memory.
+ *   - Compute calls are asynchronous on the caller's HIP stream.  Only ss_plan_check
+ *     and ss_count_pairs block (they read device counters back).
+ *   - Gradient outputs are overwritten, not accumulated into.
+ *   - Pixel (i, j) of a view (column i, row j) samples the image-plane point
+ *     (i + 0.5, j + 0.5).  Per-pixel outputs of all views are concatenated: view v
+ *     owns pixels [pix_off[v], pix_off[v+1]) with pix_off the running sum of W*H; a
+ *     C-channel output stores view v as planar [C][H][W] starting at C*pix_off[v].
+ *   - World coordinates are metres (scene centred near the origin for FP32
+ *     conditioning); F_xy maps world metres to pixels.
+ */
+#ifndef SATSPLAT_H
+#define SATSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ss_status;
+#define SS_OK               0
+#define SS_ERR_INVALID_ARG (-1)   /* bad pointer, size, setting or state                 */
+#define SS_ERR_CAPACITY    (-2)   /* workspace too small for the pairs this input needs   */
+#define SS_ERR_HIP         (-3)   /* a HIP runtime call failed                            */
+#define SS_ERR_UNSUPPORTED (-4)   /* device is not gfx950, or a setting outside the range */
+#define SS_ERR_STATE       (-5)   /* call order violated (e.g. backward before forward)   */
+
+typedef struct ss_context ss_context;
+typedef struct ss_plan ss_plan;
+typedef struct ihipStream_t *ss_stream;   /* hipStream_t; NULL = default stream */
+
+/* Rasterizer constants.  alpha_min and T_min are the stated workload values; the rest
+ * are readings where the paper gives no number (documented with the design). */
+typedef struct ss_raster_settings {
+    uint32_t struct_size;   /* sizeof(ss_raster_settings)                              */
+    int32_t  tile_size;     /* 8, 16 (paper default, Sec. 3.2) or 32                    */
+    int32_t  batch_depth;   /* surfel records staged in LDS per batch: 32,64,128,256    */
+    float    alpha_min;     /* skip a surfel at a pixel when alpha < alpha_min (1/255)  */
+    float    alpha_max;     /* alpha = min(alpha_max, o * G) (0.99)                     */
+    float    T_min;         /* stop before transmittance would drop below T_min (1e-4) */
+    float    lowpass_sigma; /* sigma of the screen-space low-pass floor, px (sqrt(2)/2) */
+    int32_t  lowpass_mode;  /* 0: floor applied to every surfel; 1: degenerate only     */
+    float    det_rel_eps;   /* degenerate iff |det T| <= eps * |T|_F^2 (1e-6)            */
+    float    esm_c;         /* exponential-shadow-map sharpness, 1/m (2.0)              */
+    float    esm_bias;      /* shadow depth bias, m (0.5)                               */
+    int32_t  sun_map_size;  /* S: sun-view depth map is S x S (1024)                    */
+} ss_raster_settings;
+
+/* Surfels, structure of arrays, FP32 device memory (Sec. 3.1 2DGS parameterisation).
+ * Activations (exp of log-scales, sigmoid of opacity, quaternion -> axes) are applied
+ * by the caller before the call. */
+typedef struct ss_surfels {
+    int64_t      n;
+    const float *mean;      /* [n,3] centre p_k, metres                                 */
+    const float *t_u;       /* [n,3] tangent axis (unit)                                */
+    const float *t_v;       /* [n,3] tangent axis (unit)                                */
+    const float *scale;     /* [n,2] s_u, s_v, metres (linear)                          */
+    const float *opacity;   /* [n]   in (0,1)                                           */
+    const float *albedo;    /* [n,3] linear RGB                                         */
+} ss_surfels;
+
+/* Views: affine cameras and per-image radiometry (Sec. 3.1, 3.3).  width/height are
+ * HOST arrays fixed at plan creation; the rest are device pointers read at call time. */
+typedef struct ss_views {
+    int32_t      n;
+    const int32_t *width;   /* host [n] */
+    const int32_t *height;  /* host [n] */
+    const float *Fxy;       /* [n,2,4] initial camera rows [B_xy | b_xy], world m -> px */
+    const float *dF;        /* [n,2,4] learnable delta, or NULL (= 0)                    */
+    const float *colC;      /* [n,3,3] per-image colour gain C, or NULL (= I)            */
+    const float *colc;      /* [n,3]   per-image colour bias c, or NULL (= 0)            */
+    const float *ambient;   /* [n,3]   ambient light L_a, or NULL (= 0)                  */
+    const float *sun;       /* [n,2]   sun (azimuth phi, elevation theta), radians, phi
+                                       from world +x towards +y; NULL if no shadow pass */
+    float        b_z;       /* max altitude: depth is b_z - z (Eq. depth_affine_camera)  */
+} ss_views;
+
+/* ---------------------------------------------------------------- lifecycle */
+const char *ss_last_error(void);
+void        ss_default_settings(ss_raster_settings *out);
+
+/* Create a context on HIP device `device`; fails with SS_ERR_UNSUPPORTED unless the
+ * device is gfx950. */
+ss_status ss_context_create(int32_t device, ss_context **out);
+ss_status ss_context_destroy(ss_context *ctx);
+
+/* A plan fixes the surfel count, the view sizes and the settings.  Views must be
+ * 1..32767 pixels on each side.  Nothing is allocated on the device. */
+ss_status ss_plan_create(ss_context *ctx, int64_t n_surfels, int32_t n_views,
+                         const int32_t *width, const int32_t *height,
+                         const ss_raster_settings *settings, ss_plan **out);
+ss_status ss_plan_destroy(ss_plan *plan);
+
+/* Change tile size / batch depth / thresholds of an existing plan (same workspace;
+ * the workspace is always sized for the smallest tile size). */
+ss_status ss_plan_set_settings(ss_plan *plan, const ss_raster_settings *settings);
+
+/* Workspace bytes for capacities of `main_pairs` (tile, surfel) pairs over all main
+ * views and `sun_pairs` over all sun views.  Capacities may be 0 (then only
+ * ss_count_pairs may run). */
+ss_status ss_plan_workspace_size(ss_plan *plan, int64_t main_pairs, int64_t sun_pairs,
+                                 size_t *bytes);
+
+/* Bind caller-owned device memory (256-byte aligned, >= the queried size) as the
+ * plan's workspace.  The plan keeps the binning of the last forward in it for the
+ * backward, so the workspace must stay alive and untouched between the two. */
+ss_status ss_plan_bind_workspace(ss_plan *plan, void *workspace, size_t bytes,
+                                 int64_t main_pairs, int64_t sun_pairs);
+
+/* Count the (tile, surfel) pairs the given surfels and cameras need (main views, and
+ * sun views when views->sun != NULL; else *sun_pairs = 0).  Blocks on `stream`. */
+ss_status ss_count_pairs(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                         int64_t *main_pairs, int64_t *sun_pairs, ss_stream stream);
+
+/* Read the capacity-overflow state of the last calls (blocks on `stream`).
+ * *overflowed = 1 if a forward or shadow pass needed more pairs than bound; its
+ * outputs are then incomplete (memory-safe) and must be recomputed after rebinding
+ * a larger workspace.  *main_pairs / *sun_pairs: pairs needed by the last calls. */
+ss_status ss_plan_check(ss_plan *plan, int32_t *overflowed, int64_t *main_pairs,
+                        int64_t *sun_pairs, ss_stream stream);
+
+/* ------------------------------------------------------------------ forward
+ * Rasterize all views (Sec. 3.2): per-surfel projection (Eqs. affine2dgs_Qq,
+ * depth_affine_camera) with F' = F + dF (Sec. 3.3), centre-depth order, 16x16 (or
+ * tile_size) binning, front-to-back compositing (Eq. rasterization) of albedo, sun
+ * visibility, depth and normal, then the image formation (Eq. image_formation).
+ *   vis      [n_views, n] per-view per-surfel sun visibility in [0,1] composited as the
+ *            V channel, or NULL: then V == 1 everywhere (no shadows, I = C A + c).
+ * Outputs (all required):
+ *   image    [3 * P] I,   albedo_out [3 * P] A,   vis_out [P] V (1.0 if vis == NULL),
+ *   depth    [P] D = sum w z (unnormalised; background contributes 0),
+ *   normal   [3 * P] world-space N = sum w n,  T_final [P],
+ *   last     [P] int32: 1 + position, in the pixel's tile list, of its last contributor.
+ * P = sum of width*height.  albedo_out, vis_out, T_final and last are the saved state
+ * the backward needs. */
+ss_status ss_forward(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                     const float *vis, float *image, float *albedo_out, float *vis_out,
+                     float *depth, float *normal, float *T_final, int32_t *last,
+                     ss_stream stream);
+
+/* ----------------------------------------------------------------- backward
+ * Adjoint of ss_forward for the same surfels/views/vis (the plan must hold that
+ * forward's binning).  Upstream gradients d_image [3P], d_depth [P], d_normal [3P];
+ * each may be NULL (= 0).  Transmittance is recomputed back to front from T_final,
+ * no per-pixel lists are stored.  Outputs (overwritten; all required):
+ *   d_mean [n,3], d_t_u [n,3], d_t_v [n,3], d_scale [n,2], d_opacity [n],
+ *   d_albedo [n,3]  (summed over views),
+ *   d_dF [n_views,2,4], d_colC [n_views,3,3], d_colc [n_views,3], d_ambient [n_views,3].
+ * vis is a stop-gradient input (no gradient is returned for it). */
+ss_status ss_backward(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                      const float *vis, const float *albedo_out, const float *vis_out,
+                      const float *T_final, const int32_t *last, const float *d_image,
+                      const float *d_depth, const float *d_normal, float *d_mean,
+                      float *d_t_u, float *d_t_v, float *d_scale, float *d_opacity,
+                      float *d_albedo, float *d_dF, float *d_colC, float *d_colc,
+                      float *d_ambient, ss_stream stream);
+
+/* -------------------------------------------------------------- shadow pass
+ * Geometric sun-view shadow map (Sec. 3.3 Eq. sun_camera_Bxy, Supp. A; Sec. 3.1 soft
+ * shadow test).  Per view: sun camera B_sun = lam * B'_xy (I - [0 0 s]) with
+ * s = (cos phi / tan theta, sin phi / tan theta, 1) and a viewport (lam, offset) that
+ * maps the flattened surfel-centre bounding box onto the central 98 % of an S x S map;
+ * depth-only compositing of the same surfels in the same depth order over a background
+ * at z_far = b_z - min z + 10 m; then per surfel k the 3x3 exponential-shadow-map test
+ *   vis[v,k] = min(1, mean_t exp(esm_c (D_t - (b_z - p_k,z) + esm_bias))).
+ * Requires views->sun.  Outputs: vis [n_views, n]; sun_depth [n_views, S, S] or NULL.
+ * The main-view binning held for the backward is not touched. */
+ss_status ss_shadow_plain(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                          float *sun_depth, float *vis, ss_stream stream);
+
+/* ---------------------------------------------------------- debug / testing
+ * Copy out the binning of the last forward (which = 0) or shadow pass (which = 1):
+ *   order       [n]           uint32 surfel indices in centre-depth order
+ *   surf_tiles  [n_views,n,4] int32 tile range tx_lo,tx_hi,ty_lo,ty_hi (lo>hi: none)
+ *   tile_ranges [n_tiles,2]   uint32 [start,end) into tile_lists, n_tiles over all
+ *                             views in view order, row-major tiles inside a view
+ *   tile_lists  [pairs]       uint32 surfel indices (pairs = *n_pairs)
+ *   records     [n_views,n,24] float projected-surfel records, or NULL
+ * *n_tiles and *n_pairs (host) receive the sizes; any output pointer may be NULL. */
+ss_status ss_debug_binning(ss_plan *plan, int32_t which, uint32_t *order,
+                           int32_t *surf_tiles, uint32_t *tile_ranges,
+                           uint32_t *tile_lists, float *records, int64_t *n_tiles,
+                           int64_t *n_pairs, ss_stream stream);
+
+/* Sun cameras of the last shadow pass: [n_views, 9] doubles B_sun (2x3 row-major),
+ * b_sun (2), z_far (host memory; blocks on stream). */
+ss_status ss_debug_sun_cameras(ss_plan *plan, double *out, ss_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SATSPLAT_H */

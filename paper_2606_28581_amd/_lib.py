@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in include/satsplat.h (argument marshalling only).
+
+Every step of the hot path runs in libsatsplat.so; nothing here computes.  Loading
+fails loudly when the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsatsplat.so")
+
+SS_OK = 0
+SS_ERR_INVALID_ARG = -1
+SS_ERR_CAPACITY = -2
+SS_ERR_HIP = -3
+SS_ERR_UNSUPPORTED = -4
+SS_ERR_STATE = -5
+
+
+class RasterSettings(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("tile_size", C.c_int32),
+                ("batch_depth", C.c_int32), ("alpha_min", C.c_float),
+                ("alpha_max", C.c_float), ("T_min", C.c_float), ("lowpass_sigma", C.c_float),
+                ("lowpass_mode", C.c_int32), ("det_rel_eps", C.c_float), ("esm_c", C.c_float),
+                ("esm_bias", C.c_float), ("sun_map_size", C.c_int32)]
+
+
+class Surfels(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("t_u", C.c_void_p),
+                ("t_v", C.c_void_p), ("scale", C.c_void_p), ("opacity", C.c_void_p),
+                ("albedo", C.c_void_p)]
+
+
+class Views(C.Structure):
+    _fields_ = [("n", C.c_int32), ("width", C.POINTER(C.c_int32)),
+                ("height", C.POINTER(C.c_int32)), ("Fxy", C.c_void_p), ("dF", C.c_void_p),
+                ("colC", C.c_void_p), ("colc", C.c_void_p), ("ambient", C.c_void_p),
+                ("sun", C.c_void_p), ("b_z", C.c_float)]
+
+
+_P = C.c_void_p
+_I64P = C.POINTER(C.c_int64)
+_SIGS = {
+    "ss_last_error": (C.c_char_p, []),
+    "ss_default_settings": (None, [C.POINTER(RasterSettings)]),
+    "ss_context_create": (C.c_int32, [C.c_int32, C.POINTER(_P)]),
+    "ss_context_destroy": (C.c_int32, [_P]),
+    "ss_plan_create": (C.c_int32, [_P, C.c_int64, C.c_int32, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int32), C.POINTER(RasterSettings),
+                                   C.POINTER(_P)]),
+    "ss_plan_destroy": (C.c_int32, [_P]),
+    "ss_plan_set_settings": (C.c_int32, [_P, C.POINTER(RasterSettings)]),
+    "ss_plan_workspace_size": (C.c_int32, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ss_plan_bind_workspace": (C.c_int32, [_P, _P, C.c_size_t, C.c_int64, C.c_int64]),
+    "ss_count_pairs": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _I64P, _I64P, _P]),
+    "ss_plan_check": (C.c_int32, [_P, C.POINTER(C.c_int32), _I64P, _I64P, _P]),
+    "ss_forward": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P, _P, _P,
+                               _P, _P, _P, _P]),
+    "ss_backward": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P, _P, _P,
+                                _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ss_shadow_plain": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P]),
+    "ss_debug_binning": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _I64P, _I64P, _P]),
+    "ss_debug_sun_cameras": (C.c_int32, [_P, _P, _P]),
+}
+
+_lib = None
+
+
+class SatSplatError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed with status {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libsatsplat.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def call(name, *args):
+    """Call an ss_* entry point; raise SatSplatError on a negative status."""
+    lib = load()
+    st = getattr(lib, name)(*args)
+    if st is not None and st != SS_OK:
+        raise SatSplatError(name, st, lib.ss_last_error().decode())
+    return st
+
+
+def declared_functions(header_path):
+    """Names of the functions declared in a public header (for the export test)."""
+    import re
+    text = open(header_path).read()
+    return sorted(set(re.findall(r"\b(ss_[a-z_]+)\s*\(", text)))
+
+
+# Aliases with the C names, for callers who prefer the flat ABI.
+def __getattr__(name):
+    if name.startswith("ss_"):
+        lib = load()
+        return getattr(lib, name)
+    raise AttributeError(name)

@@ -1,0 +1,613 @@
+// C-ABI layer of the SatSplat gfx950 hot path: validation, the plan and its workspace,
+// and the order in which the kernels of one call run on the caller's stream.
+#include "satsplat.h"
+#include "ss_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ss;
+
+namespace {
+
+thread_local std::string g_err;
+
+ss_status fail(ss_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define SS_HIP(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(SS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int bits_for(int64_t count)
+{
+    int b = 0;
+    while (b < 32 && (int64_t(1) << b) < count) ++b;
+    return b;
+}
+
+}  // namespace
+
+struct ss_context {
+    int device = 0;
+    int cus = 0;
+    std::string arch;
+};
+
+// Offsets (bytes) of every buffer inside the workspace.
+struct Layout {
+    size_t views_main, views_sun, suncam, counters, flags;
+    size_t mk_a, mk_b, mv_a, mv_b, sorted_main;
+    size_t sk_a, sk_b, sv_a, sv_b, sorted_sun;
+    size_t rec_main, tiles_main, counts_main, offs_main, scanparts;
+    size_t pk_a, pv_a, pk_b, pv_b, ranges_main, recgrad, colour_parts, dF_parts;
+    size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
+    size_t sun_depth, bounds, radix_temp;
+    size_t total;
+};
+
+struct ss_plan {
+    ss_context *ctx = nullptr;
+    ss_raster_settings st{};
+    int64_t n = 0;
+    int32_t nv = 0;
+    std::vector<int32_t> W, H;
+    std::vector<ViewDesc> vmain, vsun;
+    int32_t tiles_main = 0, tiles_sun = 0;          // for the current tile size
+    int32_t tiles_main_max = 0, tiles_sun_max = 0;  // for the smallest tile size (8)
+    int64_t P = 0;
+    int64_t cap_main = 0, cap_sun = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout L{};
+    bool fwd_valid = false, sun_valid = false;
+    uint32_t *order_main = nullptr, *order_sun = nullptr;
+    uint32_t *lists_main = nullptr, *lists_sun = nullptr;
+    template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+static void build_views(ss_plan *p)
+{
+    const int ts = p->st.tile_size;
+    const int S = p->st.sun_map_size;
+    p->vmain.resize(p->nv);
+    p->vsun.resize(p->nv);
+    int64_t pix = 0;
+    int32_t toff = 0, soff = 0;
+    for (int v = 0; v < p->nv; ++v) {
+        ViewDesc d{};
+        d.W = p->W[v]; d.H = p->H[v];
+        d.tiles_x = (d.W + ts - 1) / ts; d.tiles_y = (d.H + ts - 1) / ts;
+        d.pix_off = pix; d.tile_off = toff;
+        pix += (int64_t)d.W * d.H;
+        toff += d.tiles_x * d.tiles_y;
+        p->vmain[v] = d;
+        ViewDesc s{};
+        s.W = S; s.H = S;
+        s.tiles_x = (S + ts - 1) / ts; s.tiles_y = s.tiles_x;
+        s.pix_off = (int64_t)v * S * S; s.tile_off = soff;
+        soff += s.tiles_x * s.tiles_y;
+        p->vsun[v] = s;
+    }
+    p->P = pix;
+    p->tiles_main = toff;
+    p->tiles_sun = soff;
+}
+
+static void max_tiles(ss_plan *p)
+{
+    int64_t tm = 0, tsn = 0;
+    const int S = p->st.sun_map_size;
+    for (int v = 0; v < p->nv; ++v) {
+        tm += (int64_t)((p->W[v] + 7) / 8) * ((p->H[v] + 7) / 8);
+        tsn += (int64_t)((S + 7) / 8) * ((S + 7) / 8);
+    }
+    p->tiles_main_max = (int32_t)tm;
+    p->tiles_sun_max = (int32_t)tsn;
+}
+
+static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += align256(bytes); return r; };
+    const size_t n = (size_t)p->n, nv = (size_t)p->nv, vn = n * nv;
+    const size_t S = (size_t)p->st.sun_map_size;
+    L.views_main = take(nv * sizeof(ViewDesc));
+    L.views_sun = take(nv * sizeof(ViewDesc));
+    L.suncam = take(nv * sizeof(SunCam));
+    L.counters = take(16 * sizeof(unsigned long long));
+    L.flags = take(16 * sizeof(uint32_t));
+    L.mk_a = take(n * 4); L.mk_b = take(n * 4); L.mv_a = take(n * 4); L.mv_b = take(n * 4);
+    L.sorted_main = take(n * 16 * 4);
+    L.sk_a = take(n * 4); L.sk_b = take(n * 4); L.sv_a = take(n * 4); L.sv_b = take(n * 4);
+    L.sorted_sun = take(n * 16 * 4);
+    L.rec_main = take(vn * kRecFloats * 4);
+    L.tiles_main = take(vn * sizeof(short4));
+    L.counts_main = take(vn * 4);
+    L.offs_main = take((vn + 1) * 4);
+    L.scanparts = take(scan_temp_elems((int64_t)vn) * 4);
+    L.pk_a = take((size_t)cm * 4); L.pv_a = take((size_t)cm * 4);
+    L.pk_b = take((size_t)cm * 4); L.pv_b = take((size_t)cm * 4);
+    L.ranges_main = take((size_t)p->tiles_main_max * 8);
+    L.recgrad = take(vn * kGradFloats * 4);
+    L.colour_parts = take((size_t)p->tiles_main_max * 16 * 4);
+    L.dF_parts = take((size_t)project_bwd_blocks(p->n) * nv * 8 * 4);
+    L.rec_sun = take(vn * kRecFloats * 4);
+    L.tiles_sun = take(vn * sizeof(short4));
+    L.counts_sun = take(vn * 4);
+    L.offs_sun = take((vn + 1) * 4);
+    L.qk_a = take((size_t)cs * 4); L.qv_a = take((size_t)cs * 4);
+    L.qk_b = take((size_t)cs * 4); L.qv_b = take((size_t)cs * 4);
+    L.ranges_sun = take((size_t)p->tiles_sun_max * 8);
+    L.sun_depth = take(nv * S * S * 4);
+    L.bounds = take((size_t)bounds_blocks(p->n) * 6 * 8);
+    L.radix_temp = take(radix_temp_bytes(std::max<int64_t>(p->n, std::max(cm, cs))));
+    L.total = o;
+    return L;
+}
+
+static ss_status check_settings(const ss_raster_settings *s)
+{
+    if (!s) return fail(SS_ERR_INVALID_ARG, "settings is NULL");
+    if (s->struct_size != sizeof(ss_raster_settings))
+        return fail(SS_ERR_INVALID_ARG, "settings.struct_size mismatch");
+    if (s->tile_size != 8 && s->tile_size != 16 && s->tile_size != 32)
+        return fail(SS_ERR_UNSUPPORTED, "tile_size must be 8, 16 or 32");
+    if (s->batch_depth < 1 || s->batch_depth > 256)
+        return fail(SS_ERR_UNSUPPORTED, "batch_depth must be in [1, 256]");
+    if (!(s->alpha_min > 0.f && s->alpha_min < 1.f) || !(s->alpha_max >= s->alpha_min) ||
+        !(s->alpha_max < 1.f) || !(s->T_min > 0.f && s->T_min < 1.f) ||
+        !(s->lowpass_sigma > 0.f) || !(s->det_rel_eps >= 0.f) ||
+        (s->lowpass_mode != 0 && s->lowpass_mode != 1) || !(s->esm_c > 0.f))
+        return fail(SS_ERR_INVALID_ARG, "threshold setting out of range");
+    if (s->sun_map_size < 8 || s->sun_map_size > 16384)
+        return fail(SS_ERR_INVALID_ARG, "sun_map_size must be in [8, 16384]");
+    return SS_OK;
+}
+
+static RasterConsts consts(const ss_raster_settings &s)
+{
+    RasterConsts rc{};
+    rc.alpha_min = s.alpha_min;
+    rc.alpha_max = s.alpha_max;
+    rc.T_min = s.T_min;
+    const double sig = (double)s.lowpass_sigma;
+    rc.inv_s2 = (float)(1.0 / (sig * sig));
+    rc.lowpass_mode = s.lowpass_mode;
+    rc.batch = s.batch_depth;
+    rc.esm_c = s.esm_c;
+    rc.esm_bias = s.esm_bias;
+    rc.alpha_min_d = (double)s.alpha_min;
+    rc.sigma_d = sig;
+    rc.det_rel_eps_d = (double)s.det_rel_eps;
+    return rc;
+}
+
+static ss_status check_call(ss_plan *p, const ss_surfels *s, const ss_views *v)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->ws) return fail(SS_ERR_STATE, "no workspace bound");
+    if (!s || !v) return fail(SS_ERR_INVALID_ARG, "surfels or views is NULL");
+    if (s->n != p->n) return fail(SS_ERR_INVALID_ARG, "surfel count differs from the plan");
+    if (v->n != p->nv) return fail(SS_ERR_INVALID_ARG, "view count differs from the plan");
+    if (p->n > 0 && (!s->mean || !s->t_u || !s->t_v || !s->scale || !s->opacity || !s->albedo))
+        return fail(SS_ERR_INVALID_ARG, "a surfel array is NULL");
+    if (!v->Fxy) return fail(SS_ERR_INVALID_ARG, "views.Fxy is NULL");
+    if (!std::isfinite(v->b_z)) return fail(SS_ERR_INVALID_ARG, "b_z is not finite");
+    if (v->width && v->height)
+        for (int i = 0; i < p->nv; ++i)
+            if (v->width[i] != p->W[i] || v->height[i] != p->H[i])
+                return fail(SS_ERR_INVALID_ARG, "view sizes differ from the plan");
+    if (hipSetDevice(p->ctx->device) != hipSuccess)
+        return fail(SS_ERR_HIP, "hipSetDevice failed");
+    return SS_OK;
+}
+
+// Centre-depth order and the gather of surfel parameters into depth-rank order.
+static ss_status prepare(ss_plan *p, const ss_surfels *s, const ss_views *v, bool sun,
+                         uint32_t **order_out, float **sorted_out, hipStream_t st)
+{
+    const Layout &L = p->L;
+    uint32_t *ka = p->at<uint32_t>(sun ? L.sk_a : L.mk_a), *kb = p->at<uint32_t>(sun ? L.sk_b : L.mk_b);
+    uint32_t *va = p->at<uint32_t>(sun ? L.sv_a : L.mv_a), *vb = p->at<uint32_t>(sun ? L.sv_b : L.mv_b);
+    float *sorted = p->at<float>(sun ? L.sorted_sun : L.sorted_main);
+    SS_HIP(launch_depth_keys(s->mean, p->n, v->b_z, ka, va, st));
+    bool in_b = false;
+    SS_HIP(radix_sort_pairs(ka, va, kb, vb, p->n, nullptr, p->n, 32, p->at<void>(L.radix_temp),
+                            &in_b, st));
+    uint32_t *order = in_b ? vb : va;
+    SurfelPtrs sp{s->mean, s->t_u, s->t_v, s->scale, s->opacity, s->albedo, p->n};
+    SS_HIP(launch_gather_params(order, sp, sorted, st));
+    *order_out = order;
+    *sorted_out = sorted;
+    return SS_OK;
+}
+
+// Projection + pair-count scan (+ emission, tile sort and ranges when `bin`).
+static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32_t *order,
+                           const float *sorted, const float *vis, bool bin, hipStream_t st)
+{
+    const Layout &L = p->L;
+    const RasterConsts rc = consts(p->st);
+    const ViewDesc *views = p->at<ViewDesc>(sun ? L.views_sun : L.views_main);
+    float *rec = p->at<float>(sun ? L.rec_sun : L.rec_main);
+    short4 *tiles = p->at<short4>(sun ? L.tiles_sun : L.tiles_main);
+    uint32_t *counts = p->at<uint32_t>(sun ? L.counts_sun : L.counts_main);
+    uint32_t *offs = p->at<uint32_t>(sun ? L.offs_sun : L.offs_main);
+    unsigned long long *counters = p->at<unsigned long long>(L.counters);
+    uint32_t *flags = p->at<uint32_t>(L.flags);
+    const int64_t cap = sun ? p->cap_sun : p->cap_main;
+    SS_HIP(launch_project(sorted, p->n, order, p->nv, views, v->Fxy, sun ? nullptr : v->dF,
+                          sun ? p->at<SunCam>(L.suncam) : nullptr, sun ? nullptr : vis, v->b_z,
+                          p->st.tile_size, rc, rec, tiles, counts, st));
+    SS_HIP(scan_pair_counts(counts, p->n, p->nv, offs, p->at<uint32_t>(L.scanparts), counters,
+                            sun ? 1 : 0, flags + (sun ? 1 : 0), bin ? (uint64_t)cap : ~0ull, st));
+    if (!bin) return SS_OK;
+    uint32_t *ka = p->at<uint32_t>(sun ? L.qk_a : L.pk_a), *va = p->at<uint32_t>(sun ? L.qv_a : L.pv_a);
+    uint32_t *kb = p->at<uint32_t>(sun ? L.qk_b : L.pk_b), *vb = p->at<uint32_t>(sun ? L.qv_b : L.pv_b);
+    SS_HIP(launch_emit(order, p->n, p->nv, views, tiles, counts, offs, (uint64_t)cap, ka, va, st));
+    const int32_t ntiles = sun ? p->tiles_sun : p->tiles_main;
+    bool in_b = false;
+    SS_HIP(radix_sort_pairs(ka, va, kb, vb, cap, counters + (sun ? 1 : 0), 0, bits_for(ntiles),
+                            p->at<void>(L.radix_temp), &in_b, st));
+    uint32_t *keys = in_b ? kb : ka;
+    uint32_t *lists = in_b ? vb : va;
+    SS_HIP(launch_ranges(keys, counters + (sun ? 1 : 0), cap, ntiles,
+                         p->at<uint32_t>(sun ? L.ranges_sun : L.ranges_main), st));
+    if (sun) p->lists_sun = lists; else p->lists_main = lists;
+    return SS_OK;
+}
+
+static ss_status upload_views(ss_plan *p)
+{
+    if (!p->ws) return SS_OK;
+    SS_HIP(hipSetDevice(p->ctx->device));
+    SS_HIP(hipMemcpy(p->at<void>(p->L.views_main), p->vmain.data(), p->nv * sizeof(ViewDesc),
+                     hipMemcpyHostToDevice));
+    SS_HIP(hipMemcpy(p->at<void>(p->L.views_sun), p->vsun.data(), p->nv * sizeof(ViewDesc),
+                     hipMemcpyHostToDevice));
+    SS_HIP(hipMemset(p->at<void>(p->L.counters), 0, 16 * sizeof(unsigned long long)));
+    SS_HIP(hipMemset(p->at<void>(p->L.flags), 0, 16 * sizeof(uint32_t)));
+    return SS_OK;
+}
+
+// ======================================================================= C ABI
+extern "C" {
+
+const char *ss_last_error(void) { return g_err.c_str(); }
+
+void ss_default_settings(ss_raster_settings *out)
+{
+    if (!out) return;
+    std::memset(out, 0, sizeof *out);
+    out->struct_size = sizeof(ss_raster_settings);
+    out->tile_size = 16;
+    out->batch_depth = 64;
+    out->alpha_min = 1.0f / 255.0f;
+    out->alpha_max = 0.99f;
+    out->T_min = 1e-4f;
+    out->lowpass_sigma = 0.70710678f;
+    out->lowpass_mode = 0;
+    out->det_rel_eps = 1e-6f;
+    out->esm_c = 2.0f;
+    out->esm_bias = 0.5f;
+    out->sun_map_size = 1024;
+}
+
+ss_status ss_context_create(int32_t device, ss_context **out)
+{
+    if (!out) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(SS_ERR_HIP, "no HIP device");
+    if (device < 0 || device >= count) return fail(SS_ERR_INVALID_ARG, "device out of range");
+    hipDeviceProp_t prop;
+    SS_HIP(hipGetDeviceProperties(&prop, device));
+    std::string arch = prop.gcnArchName;
+    if (arch.rfind("gfx950", 0) != 0)
+        return fail(SS_ERR_UNSUPPORTED, "device is " + arch + ", this library is built for gfx950");
+    auto *c = new ss_context;
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    c->arch = arch;
+    *out = c;
+    return SS_OK;
+}
+
+ss_status ss_context_destroy(ss_context *ctx)
+{
+    delete ctx;
+    return SS_OK;
+}
+
+ss_status ss_plan_create(ss_context *ctx, int64_t n_surfels, int32_t n_views,
+                         const int32_t *width, const int32_t *height,
+                         const ss_raster_settings *settings, ss_plan **out)
+{
+    if (!out) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(SS_ERR_INVALID_ARG, "context is NULL");
+    if (n_surfels < 0 || n_surfels > 0x7FFFFFFF)
+        return fail(SS_ERR_INVALID_ARG, "n_surfels must be in [0, 2^31)");
+    if (n_views < 1 || n_views > 65535) return fail(SS_ERR_INVALID_ARG, "n_views must be in [1, 65535]");
+    if (!width || !height) return fail(SS_ERR_INVALID_ARG, "width/height is NULL");
+    ss_status e = check_settings(settings);
+    if (e != SS_OK) return e;
+    int64_t tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        if (width[v] < 1 || width[v] > 32767 || height[v] < 1 || height[v] > 32767)
+            return fail(SS_ERR_INVALID_ARG, "view sides must be in [1, 32767]");
+        tiles += (int64_t)((width[v] + 7) / 8) * ((height[v] + 7) / 8);
+    }
+    const int64_t S = settings->sun_map_size;
+    if (tiles > 0x7FFFFFFF || (int64_t)n_views * ((S + 7) / 8) * ((S + 7) / 8) > 0x7FFFFFFF)
+        return fail(SS_ERR_INVALID_ARG, "too many tiles");
+    auto *p = new ss_plan;
+    p->ctx = ctx;
+    p->st = *settings;
+    p->n = n_surfels;
+    p->nv = n_views;
+    p->W.assign(width, width + n_views);
+    p->H.assign(height, height + n_views);
+    build_views(p);
+    max_tiles(p);
+    *out = p;
+    return SS_OK;
+}
+
+ss_status ss_plan_destroy(ss_plan *plan)
+{
+    delete plan;
+    return SS_OK;
+}
+
+ss_status ss_plan_set_settings(ss_plan *p, const ss_raster_settings *settings)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    ss_status e = check_settings(settings);
+    if (e != SS_OK) return e;
+    if (settings->sun_map_size != p->st.sun_map_size)
+        return fail(SS_ERR_INVALID_ARG, "sun_map_size is fixed at plan creation");
+    p->st = *settings;
+    build_views(p);
+    p->fwd_valid = p->sun_valid = false;
+    return upload_views(p);
+}
+
+ss_status ss_plan_workspace_size(ss_plan *p, int64_t main_pairs, int64_t sun_pairs, size_t *bytes)
+{
+    if (!p || !bytes) return fail(SS_ERR_INVALID_ARG, "plan or bytes is NULL");
+    if (main_pairs < 0 || sun_pairs < 0 || main_pairs > 0xFFFFFFFFll || sun_pairs > 0xFFFFFFFFll)
+        return fail(SS_ERR_INVALID_ARG, "pair capacity must be in [0, 2^32)");
+    *bytes = make_layout(p, main_pairs, sun_pairs).total;
+    return SS_OK;
+}
+
+ss_status ss_plan_bind_workspace(ss_plan *p, void *workspace, size_t bytes, int64_t main_pairs,
+                                 int64_t sun_pairs)
+{
+    if (!p || !workspace) return fail(SS_ERR_INVALID_ARG, "plan or workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(SS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (main_pairs < 0 || sun_pairs < 0 || main_pairs > 0xFFFFFFFFll || sun_pairs > 0xFFFFFFFFll)
+        return fail(SS_ERR_INVALID_ARG, "pair capacity must be in [0, 2^32)");
+    Layout L = make_layout(p, main_pairs, sun_pairs);
+    if (bytes < L.total) return fail(SS_ERR_CAPACITY, "workspace smaller than required");
+    p->L = L;
+    p->ws = reinterpret_cast<char *>(workspace);
+    p->ws_bytes = bytes;
+    p->cap_main = main_pairs;
+    p->cap_sun = sun_pairs;
+    p->fwd_valid = p->sun_valid = false;
+    return upload_views(p);
+}
+
+ss_status ss_count_pairs(ss_plan *p, const ss_surfels *s, const ss_views *v, int64_t *main_pairs,
+                         int64_t *sun_pairs, ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint32_t *order;
+    float *sorted;
+    e = prepare(p, s, v, false, &order, &sorted, st);
+    if (e != SS_OK) return e;
+    e = bin_views(p, v, false, order, sorted, nullptr, false, st);
+    if (e != SS_OK) return e;
+    if (v->sun) {
+        e = prepare(p, s, v, true, &order, &sorted, st);
+        if (e != SS_OK) return e;
+        SS_HIP(launch_sun_cameras(s->mean, p->n, p->nv, v->Fxy, v->dF, v->sun, v->b_z,
+                                  p->st.sun_map_size, p->at<double>(p->L.bounds),
+                                  p->at<SunCam>(p->L.suncam), st));
+        e = bin_views(p, v, true, order, sorted, nullptr, false, st);
+        if (e != SS_OK) return e;
+    }
+    unsigned long long c[2] = {0, 0};
+    SS_HIP(hipMemcpyAsync(c, p->at<void>(p->L.counters), sizeof c, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
+    if (main_pairs) *main_pairs = (int64_t)c[0];
+    if (sun_pairs) *sun_pairs = v->sun ? (int64_t)c[1] : 0;
+    p->fwd_valid = p->sun_valid = false;
+    return SS_OK;
+}
+
+ss_status ss_plan_check(ss_plan *p, int32_t *overflowed, int64_t *main_pairs, int64_t *sun_pairs,
+                        ss_stream stream)
+{
+    if (!p || !p->ws) return fail(SS_ERR_STATE, "plan has no workspace");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SS_HIP(hipSetDevice(p->ctx->device));
+    unsigned long long c[2];
+    uint32_t f[2];
+    SS_HIP(hipMemcpyAsync(c, p->at<void>(p->L.counters), sizeof c, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(f, p->at<void>(p->L.flags), sizeof f, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
+    if (overflowed) *overflowed = (f[0] | f[1]) ? 1 : 0;
+    if (main_pairs) *main_pairs = (int64_t)c[0];
+    if (sun_pairs) *sun_pairs = (int64_t)c[1];
+    return SS_OK;
+}
+
+ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                     float *image, float *albedo_out, float *vis_out, float *depth,
+                     float *normal, float *T_final, int32_t *last, ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!image || !albedo_out || !vis_out || !depth || !normal || !T_final || !last)
+        return fail(SS_ERR_INVALID_ARG, "an output pointer is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    p->fwd_valid = false;
+    SS_HIP(fill_u32(p->at<uint32_t>(p->L.flags), 0u, 1, st));
+    uint32_t *order;
+    float *sorted;
+    if ((e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
+    if ((e = bin_views(p, v, false, order, sorted, vis, true, st)) != SS_OK) return e;
+    const RasterConsts rc = consts(p->st);
+    SS_HIP(launch_raster_fwd(p->st.tile_size, false, vis != nullptr, p->tiles_main, p->nv,
+                             p->at<ViewDesc>(p->L.views_main), p->at<uint32_t>(p->L.ranges_main),
+                             p->lists_main, p->at<float>(p->L.rec_main), p->n, rc, v->colC,
+                             v->colc, v->ambient, nullptr, image, albedo_out, vis_out, depth,
+                             normal, T_final, last, st));
+    p->order_main = order;
+    p->fwd_valid = true;
+    return SS_OK;
+}
+
+ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                      const float *albedo_out, const float *vis_out, const float *T_final,
+                      const int32_t *last, const float *d_image, const float *d_depth,
+                      const float *d_normal, float *d_mean, float *d_t_u, float *d_t_v,
+                      float *d_scale, float *d_opacity, float *d_albedo, float *d_dF,
+                      float *d_colC, float *d_colc, float *d_ambient, ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!p->fwd_valid) return fail(SS_ERR_STATE, "backward needs the plan's forward binning");
+    if (!albedo_out || !vis_out || !T_final || !last)
+        return fail(SS_ERR_INVALID_ARG, "a saved forward output is NULL");
+    if ((p->n > 0 && (!d_mean || !d_t_u || !d_t_v || !d_scale || !d_opacity || !d_albedo)) ||
+        !d_dF || !d_colC || !d_colc || !d_ambient)
+        return fail(SS_ERR_INVALID_ARG, "a gradient output is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Layout &L = p->L;
+    const RasterConsts rc = consts(p->st);
+    float *recgrad = p->at<float>(L.recgrad);
+    SS_HIP(fill_f32(recgrad, 0.f, p->n * (int64_t)p->nv * kGradFloats, st));
+    SS_HIP(launch_raster_bwd(p->st.tile_size, vis != nullptr, p->tiles_main, p->nv,
+                             p->at<ViewDesc>(L.views_main), p->at<uint32_t>(L.ranges_main),
+                             p->lists_main, p->at<float>(L.rec_main), p->n, rc, v->colC, v->colc,
+                             v->ambient, albedo_out, vis_out, T_final, last, d_image, d_depth,
+                             d_normal, recgrad, p->at<float>(L.colour_parts), st));
+    SS_HIP(launch_colour_reduce(p->at<float>(L.colour_parts), p->nv, p->at<ViewDesc>(L.views_main),
+                                d_colC, d_colc, d_ambient, st));
+    SS_HIP(launch_project_bwd(p->at<float>(L.sorted_main), p->n, p->order_main, p->nv, v->Fxy,
+                              v->dF, p->at<float>(L.rec_main), recgrad, d_mean, d_t_u, d_t_v,
+                              d_scale, d_opacity, d_albedo, p->at<float>(L.dF_parts), st));
+    SS_HIP(launch_dF_reduce(p->at<float>(L.dF_parts), project_bwd_blocks(p->n), p->nv, d_dF, st));
+    return SS_OK;
+}
+
+ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, float *sun_depth,
+                          float *vis, ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!v->sun) return fail(SS_ERR_INVALID_ARG, "views.sun is NULL");
+    if (!vis) return fail(SS_ERR_INVALID_ARG, "vis output is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Layout &L = p->L;
+    p->sun_valid = false;
+    SS_HIP(fill_u32(p->at<uint32_t>(L.flags) + 1, 0u, 1, st));
+    uint32_t *order;
+    float *sorted;
+    if ((e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
+    SS_HIP(launch_sun_cameras(s->mean, p->n, p->nv, v->Fxy, v->dF, v->sun, v->b_z,
+                              p->st.sun_map_size, p->at<double>(L.bounds), p->at<SunCam>(L.suncam),
+                              st));
+    if ((e = bin_views(p, v, true, order, sorted, nullptr, true, st)) != SS_OK) return e;
+    float *D = sun_depth ? sun_depth : p->at<float>(L.sun_depth);
+    const RasterConsts rc = consts(p->st);
+    SS_HIP(launch_raster_fwd(p->st.tile_size, true, false, p->tiles_sun, p->nv,
+                             p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
+                             p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
+                             nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
+                             nullptr, nullptr, nullptr, st));
+    SS_HIP(launch_shadow_query(s->mean, p->n, p->nv, p->at<SunCam>(L.suncam), D,
+                               p->st.sun_map_size, v->b_z, p->st.esm_c, p->st.esm_bias, vis, st));
+    p->order_sun = order;
+    p->sun_valid = true;
+    return SS_OK;
+}
+
+ss_status ss_debug_binning(ss_plan *p, int32_t which, uint32_t *order, int32_t *surf_tiles,
+                           uint32_t *tile_ranges, uint32_t *tile_lists, float *records,
+                           int64_t *n_tiles, int64_t *n_pairs, ss_stream stream)
+{
+    if (!p || !p->ws) return fail(SS_ERR_STATE, "plan has no workspace");
+    if (which != 0 && which != 1) return fail(SS_ERR_INVALID_ARG, "which must be 0 or 1");
+    const bool sun = which == 1;
+    if (!(sun ? p->sun_valid : p->fwd_valid)) return fail(SS_ERR_STATE, "no binning to report");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SS_HIP(hipSetDevice(p->ctx->device));
+    const Layout &L = p->L;
+    const uint32_t *ord = sun ? p->order_sun : p->order_main;
+    const int64_t nt = sun ? p->tiles_sun : p->tiles_main;
+    const int64_t cap = sun ? p->cap_sun : p->cap_main;
+    const unsigned long long *cnt = p->at<unsigned long long>(L.counters) + (sun ? 1 : 0);
+    unsigned long long k = 0;
+    SS_HIP(hipMemcpyAsync(&k, cnt, sizeof k, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
+    const int64_t npairs = (int64_t)std::min<unsigned long long>(k, (unsigned long long)cap);
+    if (n_tiles) *n_tiles = nt;
+    if (n_pairs) *n_pairs = npairs;
+    if (order && p->n > 0)
+        SS_HIP(hipMemcpyAsync(order, ord, p->n * 4, hipMemcpyDeviceToDevice, st));
+    if (surf_tiles && p->n > 0)
+        SS_HIP(launch_unpermute_tiles(ord, p->n, p->nv, p->at<short4>(sun ? L.tiles_sun : L.tiles_main),
+                                      surf_tiles, st));
+    if (tile_ranges)
+        SS_HIP(hipMemcpyAsync(tile_ranges, p->at<void>(sun ? L.ranges_sun : L.ranges_main), nt * 8,
+                              hipMemcpyDeviceToDevice, st));
+    if (tile_lists && npairs > 0)
+        SS_HIP(launch_map_through(ord, p->n, cnt, cap, sun ? p->lists_sun : p->lists_main, tile_lists,
+                                  st));
+    if (records && p->n > 0)
+        SS_HIP(launch_unpermute_rows(ord, p->n, p->nv, p->at<uint32_t>(sun ? L.rec_sun : L.rec_main),
+                                     kRecFloats, reinterpret_cast<uint32_t *>(records), st));
+    SS_HIP(hipStreamSynchronize(st));
+    return SS_OK;
+}
+
+ss_status ss_debug_sun_cameras(ss_plan *p, double *out, ss_stream stream)
+{
+    if (!p || !p->ws || !out) return fail(SS_ERR_INVALID_ARG, "plan/workspace/out missing");
+    if (!p->sun_valid) return fail(SS_ERR_STATE, "no shadow pass has run");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    std::vector<SunCam> c(p->nv);
+    SS_HIP(hipMemcpyAsync(c.data(), p->at<void>(p->L.suncam), p->nv * sizeof(SunCam),
+                          hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
+    for (int v = 0; v < p->nv; ++v) {
+        for (int k = 0; k < 6; ++k) out[9 * v + k] = c[v].B[k];
+        out[9 * v + 6] = c[v].b[0];
+        out[9 * v + 7] = c[v].b[1];
+        out[9 * v + 8] = c[v].zfar;
+    }
+    return SS_OK;
+}
+
+}  // extern "C"

