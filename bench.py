@@ -1,0 +1,226 @@
+"""Benchmark of the SatSplat hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+  sun-view shadow pass for every view (sun cameras, depth-only sun maps, per-surfel
+  soft visibility) -> forward render of every view with that visibility, colour
+  correction and camera deltas -> backward to every surfel parameter, camera delta
+  and colour term.
+Default workload: 2M surfels on a 1x1 km synthetic city, 40 affine views of uneven
+sides in [1024, 2048] px, a 1024^2 sun map per view.
+
+Prints ONE JSON line.  `value` is fwd+bwd throughput in Mpix/s over the timed steps
+(inputs resident in HBM).  `roofline` reports the dominant kernel, timed live with HIP
+events on the stream its kernels run on; `cpu_baseline` times the FP64 oracle on a
+bounded pixel sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+# FP32 vector peak without packed dual-FP32 issue (disabled in this build):
+# 256 CU x 64 FMA lanes/clk x 2 flop x 2.4 GHz.
+VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 flops per contributing (pixel, surfel) pair (FMA = 2, exp = 4):
+FLOPS_FWD_PAIR = 46
+FLOPS_BWD_PAIR = 90
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=1024)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_step_bytes(N, V, P, K, Ks, S, Nv=None, Nvs=None):
+    """Bytes the method's structure must move per step (surfels read/written once,
+    per-view records, pair lists, per-pixel images, record gradients, sun maps)."""
+    Nv = N if Nv is None else Nv
+    Nvs = N if Nvs is None else Nvs
+    per_step = 60 * N + 16 * N + 60 * N
+    fwd = 68 * Nv * V + 16 * K + 72 * K + 52 * P
+    bwd = 68 * P + 72 * K + 64 * K + 64 * Nv * V
+    sun = 44 * Nvs * V + 64 * Ks + 8 * S * S * V + 4 * N * V
+    return per_step + fwd + bwd + sun
+
+
+def cpu_baseline(scene, n_pix, seed=5):
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    W, H = int(scene["width"][0]), int(scene["height"][0])
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(W * H, size=n_pix, replace=False)).astype(np.int64)
+    scene1 = dict(scene, width=scene["width"][:1], height=scene["height"][:1],
+                  Fxy=scene["Fxy"][:1], dF=scene["dF"][:1],
+                  colC=None if scene["colC"] is None else scene["colC"][:1],
+                  colc=None if scene["colc"] is None else scene["colc"][:1],
+                  ambient=None if scene["ambient"] is None else scene["ambient"][:1])
+    st = oracle.Settings()
+    g = np.random.default_rng(seed + 1)
+    dI = g.standard_normal(3 * n_pix).astype(np.float32)
+    dD = g.standard_normal(n_pix).astype(np.float32)
+    dN = g.standard_normal(3 * n_pix).astype(np.float32)
+    t0 = time.perf_counter()
+    oracle.forward(scene1, st, sel=sel)
+    t1 = time.perf_counter()
+    oracle.backward(scene1, dI, dD, dN, st, sel=sel)
+    t2 = time.perf_counter()
+    return dict(value=n_pix / (t2 - t0) / 1e6, unit="Mpix/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{n_pix} seeded pixels of view 0 ({W}x{H}), forward {t1 - t0:.1f} s + "
+                       f"backward {t2 - t1:.1f} s, FP64 brute force over all {scene['surfels']['mean'].shape[0]} "
+                       f"surfels per pixel, no shadow pass")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU design shards views, see the design notes)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_2606_28581_amd as ss
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    spec = synth.config(args.config)
+    scene = synth.make_scene(spec)
+    log(f"[bench] scene {spec.name}: {spec.n_surfels} surfels, {len(spec.view_sizes)} views, "
+        f"generated in {time.time() - t0:.1f} s")
+    ctx = ss.Context(0)
+    surf, views = ss.scene_to_device(scene, with_sun=True)
+    has_sun = views.sun is not None
+    settings = ss.default_settings(tile_size=args.tile, batch_depth=args.batch)
+    plan = ss.Plan(ctx, surf.mean.shape[0], views.width, views.height, settings)
+    K, Ks = plan.ensure_capacity(surf, views)
+    P = views.pixels
+    N = surf.mean.shape[0]
+    V = len(views.width)
+    S = settings.sun_map_size
+    log(f"[bench] pairs main {K}, sun {Ks}, pixels {P}, workspace {plan.workspace.numel() / 2**30:.1f} GiB")
+    dev = "cuda:0"
+    f = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=dev)
+    out = dict(image=f(3 * P), albedo=f(3 * P), vis=f(P), depth=f(P), normal=f(3 * P), T=f(P),
+               last=torch.empty(P, dtype=torch.int32, device=dev))
+    grads = dict(mean=f(N, 3), t_u=f(N, 3), t_v=f(N, 3), scale=f(N, 2), opacity=f(N),
+                 albedo=f(N, 3), dF=f(V, 2, 4), colC=f(V, 3, 3), colc=f(V, 3), ambient=f(V, 3))
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(spec.seed)
+    dI = torch.randn(3 * P, generator=gen, device=dev)
+    dD = torch.randn(P, generator=gen, device=dev)
+    dN = torch.randn(3 * P, generator=gen, device=dev)
+    vis = f(V, N) if has_sun else None
+
+    def step():
+        if has_sun:
+            plan.shadow(surf, views, vis_out=vis, check=False)
+        plan.forward(surf, views, vis, out=out, check=False)
+        plan.backward(surf, views, out, dI, dD, dN, vis=vis, grads=grads)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup step {i + 1}/{args.warmup} done")
+    over, K_now, Ks_now = plan.check()
+    if over:
+        raise RuntimeError("pair capacity overflow during warmup")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    log(f"[bench] timed {args.steps} steps in {t_total:.3f} s")
+    over, _, _ = plan.check()
+    if over:
+        raise RuntimeError("pair capacity overflow in the timed region")
+    stats = plan.stats()
+    # per-stage timing pass (HIP events recorded by the library on the same stream)
+    plan.read_timing()
+    plan.set_timing(True)
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    stages = plan.read_timing()
+    plan.set_timing(False)
+    ms_step = 1e3 * t_total / args.steps
+    value = P * args.steps / t_total / 1e6
+    kern = {}
+    for name, (ms, n) in stages.items():
+        if n:
+            kern[name] = dict(avg_ms=ms / n, launches=n, share=ms / n / ms_step)
+    log("[bench] stages (avg ms / launch): " + ", ".join(f"{k} {v['avg_ms']:.3f}" for k, v in kern.items()))
+    C = stats["contrib"]
+    fwd_ms = kern["raster_fwd"]["avg_ms"]
+    bwd_ms = kern["raster_bwd"]["avg_ms"]
+    cands = {
+        "raster_fwd": (FLOPS_FWD_PAIR * C / (fwd_ms * 1e-3) / 1e12, fwd_ms),
+        "raster_bwd": (FLOPS_BWD_PAIR * C / (bwd_ms * 1e-3) / 1e12, bwd_ms),
+    }
+    dom = max(cands, key=lambda k: cands[k][1])
+    achieved = cands[dom][0]
+    roofline = dict(kernel=dom, bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TFLOPS, 1),
+                    unit="TFLOP/s", frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=None,
+                    avg_ms=round(cands[dom][1], 4),
+                    work=f"{FLOPS_FWD_PAIR if dom == 'raster_fwd' else FLOPS_BWD_PAIR} flop x "
+                         f"{C} contributing pairs per launch")
+    step_bytes = algorithmic_step_bytes(N, V, P, stats["pairs"], stats["sun_pairs"] if has_sun else 0,
+                                        S if has_sun else 0)
+    result = {
+        "metric": "fwd+bwd Mpix/s (2DGS affine raster); shadow ms/view plain vs MLP surrogate",
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "surfels": N, "views": V, "pixels": P,
+                   "sun_map": S if has_sun else 0, "tile": args.tile, "batch_depth": args.batch,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "step_hbm": dict(algorithmic_bytes=step_bytes,
+                         achieved_GBps=round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
+                         peak_GBps=HBM_PEAK_GBPS,
+                         frac=round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)),
+        "shadow_ms_per_view": round(sum(kern.get(k, {}).get("avg_ms", 0.0) for k in
+                                        ("sun_camera", "sun_project", "sun_bin", "sun_raster",
+                                         "shadow_query")) / V, 4) if has_sun else None,
+        "work": dict(pairs=stats["pairs"], contributing=C, evaluated=stats["evaluated"],
+                     sun_pairs=stats["sun_pairs"], sun_contributing=stats["sun_contrib"]),
+        "kernels": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host")
+        result["cpu_baseline"] = cpu_baseline(scene, args.cpu_pixels)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -211,6 +211,35 @@ ss_status ss_debug_binning(ss_plan *plan, int32_t which, uint32_t *order,
  * b_sun (2), z_far (host memory; blocks on stream). */
 ss_status ss_debug_sun_cameras(ss_plan *plan, double *out, ss_stream stream);
 
+/* ------------------------------------------------------------ measurement
+ * Stage timing: when enabled, the library records a HIP event pair on the call's
+ * stream around each stage below; ss_plan_read_timing blocks until the recorded
+ * events completed, adds their elapsed times to ms[stage] / launches[stage] (host
+ * arrays of SS_NUM_STAGES) and forgets them.  Stages that are a single kernel:
+ * RASTER_FWD, RASTER_BWD, PROJECT, PROJECT_BWD, SUN_RASTER, SHADOW_QUERY. */
+#define SS_STAGE_DEPTH_SORT   0   /* depth keys, 4-pass radix sort, gather into rank order */
+#define SS_STAGE_PROJECT      1   /* main-view projection + tile ranges                    */
+#define SS_STAGE_BIN          2   /* pair-count scan, emission, tile sort, tile ranges     */
+#define SS_STAGE_RASTER_FWD   3
+#define SS_STAGE_RASTER_BWD   4
+#define SS_STAGE_PROJECT_BWD  5
+#define SS_STAGE_REDUCE       6   /* gradient zeroing, colour and camera-delta reductions  */
+#define SS_STAGE_SUN_CAMERA   7   /* scene bounds + sun cameras                            */
+#define SS_STAGE_SUN_PROJECT  8
+#define SS_STAGE_SUN_BIN      9
+#define SS_STAGE_SUN_RASTER  10   /* depth-only compositing of the sun maps                */
+#define SS_STAGE_SHADOW_QUERY 11
+#define SS_NUM_STAGES        12
+ss_status ss_plan_set_timing(ss_plan *plan, int32_t enable);
+ss_status ss_plan_read_timing(ss_plan *plan, double *ms, int64_t *launches);
+const char *ss_stage_name(int32_t stage);
+
+/* Work counters of the last forward / shadow pass (blocks on stream), host int64[6]:
+ *   [0] pairs bound (tile, surfel) main views   [1] contributing (pixel, surfel) pairs
+ *   [2] evaluated (pixel, surfel) pairs after per-wave culling (main views)
+ *   [3] pairs bound, sun views   [4] contributing pairs, sun   [5] evaluated pairs, sun */
+ss_status ss_plan_stats(ss_plan *plan, int64_t *out, ss_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

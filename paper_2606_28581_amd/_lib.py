@@ -63,7 +63,13 @@ _SIGS = {
     "ss_shadow_plain": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P]),
     "ss_debug_binning": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _I64P, _I64P, _P]),
     "ss_debug_sun_cameras": (C.c_int32, [_P, _P, _P]),
+    "ss_plan_set_timing": (C.c_int32, [_P, C.c_int32]),
+    "ss_plan_read_timing": (C.c_int32, [_P, _P, _P]),
+    "ss_stage_name": (C.c_char_p, [C.c_int32]),
+    "ss_plan_stats": (C.c_int32, [_P, _P, _P]),
 }
+
+SS_NUM_STAGES = 12
 
 _lib = None
 

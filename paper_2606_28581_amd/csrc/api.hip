@@ -57,7 +57,32 @@ struct Layout {
     size_t total;
 };
 
+// HIP-event stage timer (enabled by ss_plan_set_timing).
+struct StageTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Pending { int stage; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    double ms[SS_NUM_STAGES] = {0};
+    int64_t count[SS_NUM_STAGES] = {0};
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    ~StageTimer()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
 struct ss_plan {
+    StageTimer timer;
     ss_context *ctx = nullptr;
     ss_raster_settings st{};
     int64_t n = 0;
@@ -75,6 +100,26 @@ struct ss_plan {
     uint32_t *order_main = nullptr, *order_sun = nullptr;
     uint32_t *lists_main = nullptr, *lists_sun = nullptr;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+// Records an event pair around a stage when timing is on.
+struct StageScope {
+    ss_plan *p;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    StageScope(ss_plan *p_, int stage_, hipStream_t st_) : p(p_), stage(stage_), st(st_)
+    {
+        if (p->timer.on && (a = p->timer.take()) != nullptr) (void)hipEventRecord(a, st);
+    }
+    ~StageScope()
+    {
+        if (!a) return;
+        hipEvent_t b = p->timer.take();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        p->timer.pending.push_back({stage, a, b});
+    }
 };
 
 static void build_views(ss_plan *p)
@@ -223,6 +268,7 @@ static ss_status prepare(ss_plan *p, const ss_surfels *s, const ss_views *v, boo
     uint32_t *ka = p->at<uint32_t>(sun ? L.sk_a : L.mk_a), *kb = p->at<uint32_t>(sun ? L.sk_b : L.mk_b);
     uint32_t *va = p->at<uint32_t>(sun ? L.sv_a : L.mv_a), *vb = p->at<uint32_t>(sun ? L.sv_b : L.mv_b);
     float *sorted = p->at<float>(sun ? L.sorted_sun : L.sorted_main);
+    StageScope scope(p, SS_STAGE_DEPTH_SORT, st);
     SS_HIP(launch_depth_keys(s->mean, p->n, v->b_z, ka, va, st));
     bool in_b = false;
     SS_HIP(radix_sort_pairs(ka, va, kb, vb, p->n, nullptr, p->n, 32, p->at<void>(L.radix_temp),
@@ -249,9 +295,13 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
     unsigned long long *counters = p->at<unsigned long long>(L.counters);
     uint32_t *flags = p->at<uint32_t>(L.flags);
     const int64_t cap = sun ? p->cap_sun : p->cap_main;
-    SS_HIP(launch_project(sorted, p->n, order, p->nv, views, v->Fxy, sun ? nullptr : v->dF,
-                          sun ? p->at<SunCam>(L.suncam) : nullptr, sun ? nullptr : vis, v->b_z,
-                          p->st.tile_size, rc, rec, tiles, counts, st));
+    {
+        StageScope scope(p, sun ? SS_STAGE_SUN_PROJECT : SS_STAGE_PROJECT, st);
+        SS_HIP(launch_project(sorted, p->n, order, p->nv, views, v->Fxy, sun ? nullptr : v->dF,
+                              sun ? p->at<SunCam>(L.suncam) : nullptr, sun ? nullptr : vis,
+                              v->b_z, p->st.tile_size, rc, rec, tiles, counts, st));
+    }
+    StageScope scope(p, sun ? SS_STAGE_SUN_BIN : SS_STAGE_BIN, st);
     SS_HIP(scan_pair_counts(counts, p->n, p->nv, offs, p->at<uint32_t>(L.scanparts), counters,
                             sun ? 1 : 0, flags + (sun ? 1 : 0), bin ? (uint64_t)cap : ~0ull, st));
     if (!bin) return SS_OK;
@@ -472,16 +522,22 @@ ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const f
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     p->fwd_valid = false;
     SS_HIP(fill_u32(p->at<uint32_t>(p->L.flags), 0u, 1, st));
+    unsigned long long *counters = p->at<unsigned long long>(p->L.counters);
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 2), 0u, 4, st));
     uint32_t *order;
     float *sorted;
     if ((e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
     if ((e = bin_views(p, v, false, order, sorted, vis, true, st)) != SS_OK) return e;
     const RasterConsts rc = consts(p->st);
-    SS_HIP(launch_raster_fwd(p->st.tile_size, false, vis != nullptr, p->tiles_main, p->nv,
-                             p->at<ViewDesc>(p->L.views_main), p->at<uint32_t>(p->L.ranges_main),
-                             p->lists_main, p->at<float>(p->L.rec_main), p->n, rc, v->colC,
-                             v->colc, v->ambient, nullptr, image, albedo_out, vis_out, depth,
-                             normal, T_final, last, st));
+    {
+        StageScope scope(p, SS_STAGE_RASTER_FWD, st);
+        SS_HIP(launch_raster_fwd(p->st.tile_size, false, vis != nullptr, p->tiles_main, p->nv,
+                                 p->at<ViewDesc>(p->L.views_main),
+                                 p->at<uint32_t>(p->L.ranges_main), p->lists_main,
+                                 p->at<float>(p->L.rec_main), p->n, rc, v->colC, v->colc,
+                                 v->ambient, nullptr, image, albedo_out, vis_out, depth, normal,
+                                 T_final, last, counters + 2, st));
+    }
     p->order_main = order;
     p->fwd_valid = true;
     return SS_OK;
@@ -506,17 +562,30 @@ ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
     const Layout &L = p->L;
     const RasterConsts rc = consts(p->st);
     float *recgrad = p->at<float>(L.recgrad);
-    SS_HIP(fill_f32(recgrad, 0.f, p->n * (int64_t)p->nv * kGradFloats, st));
-    SS_HIP(launch_raster_bwd(p->st.tile_size, vis != nullptr, p->tiles_main, p->nv,
-                             p->at<ViewDesc>(L.views_main), p->at<uint32_t>(L.ranges_main),
-                             p->lists_main, p->at<float>(L.rec_main), p->n, rc, v->colC, v->colc,
-                             v->ambient, albedo_out, vis_out, T_final, last, d_image, d_depth,
-                             d_normal, recgrad, p->at<float>(L.colour_parts), st));
-    SS_HIP(launch_colour_reduce(p->at<float>(L.colour_parts), p->nv, p->at<ViewDesc>(L.views_main),
-                                d_colC, d_colc, d_ambient, st));
-    SS_HIP(launch_project_bwd(p->at<float>(L.sorted_main), p->n, p->order_main, p->nv, v->Fxy,
-                              v->dF, p->at<float>(L.rec_main), recgrad, d_mean, d_t_u, d_t_v,
-                              d_scale, d_opacity, d_albedo, p->at<float>(L.dF_parts), st));
+    {
+        StageScope scope(p, SS_STAGE_REDUCE, st);
+        SS_HIP(fill_f32(recgrad, 0.f, p->n * (int64_t)p->nv * kGradFloats, st));
+    }
+    {
+        StageScope scope(p, SS_STAGE_RASTER_BWD, st);
+        SS_HIP(launch_raster_bwd(p->st.tile_size, vis != nullptr, p->tiles_main, p->nv,
+                                 p->at<ViewDesc>(L.views_main), p->at<uint32_t>(L.ranges_main),
+                                 p->lists_main, p->at<float>(L.rec_main), p->n, rc, v->colC,
+                                 v->colc, v->ambient, albedo_out, vis_out, T_final, last, d_image,
+                                 d_depth, d_normal, recgrad, p->at<float>(L.colour_parts), st));
+    }
+    {
+        StageScope scope(p, SS_STAGE_REDUCE, st);
+        SS_HIP(launch_colour_reduce(p->at<float>(L.colour_parts), p->nv,
+                                    p->at<ViewDesc>(L.views_main), d_colC, d_colc, d_ambient, st));
+    }
+    {
+        StageScope scope(p, SS_STAGE_PROJECT_BWD, st);
+        SS_HIP(launch_project_bwd(p->at<float>(L.sorted_main), p->n, p->order_main, p->nv, v->Fxy,
+                                  v->dF, p->at<float>(L.rec_main), recgrad, d_mean, d_t_u, d_t_v,
+                                  d_scale, d_opacity, d_albedo, p->at<float>(L.dF_parts), st));
+    }
+    StageScope scope(p, SS_STAGE_REDUCE, st);
     SS_HIP(launch_dF_reduce(p->at<float>(L.dF_parts), project_bwd_blocks(p->n), p->nv, d_dF, st));
     return SS_OK;
 }
@@ -532,22 +601,34 @@ ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, fl
     const Layout &L = p->L;
     p->sun_valid = false;
     SS_HIP(fill_u32(p->at<uint32_t>(L.flags) + 1, 0u, 1, st));
+    unsigned long long *counters = p->at<unsigned long long>(L.counters);
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 4), 0u, 4, st));
     uint32_t *order;
     float *sorted;
     if ((e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
-    SS_HIP(launch_sun_cameras(s->mean, p->n, p->nv, v->Fxy, v->dF, v->sun, v->b_z,
-                              p->st.sun_map_size, p->at<double>(L.bounds), p->at<SunCam>(L.suncam),
-                              st));
+    {
+        StageScope scope(p, SS_STAGE_SUN_CAMERA, st);
+        SS_HIP(launch_sun_cameras(s->mean, p->n, p->nv, v->Fxy, v->dF, v->sun, v->b_z,
+                                  p->st.sun_map_size, p->at<double>(L.bounds),
+                                  p->at<SunCam>(L.suncam), st));
+    }
     if ((e = bin_views(p, v, true, order, sorted, nullptr, true, st)) != SS_OK) return e;
     float *D = sun_depth ? sun_depth : p->at<float>(L.sun_depth);
     const RasterConsts rc = consts(p->st);
-    SS_HIP(launch_raster_fwd(p->st.tile_size, true, false, p->tiles_sun, p->nv,
-                             p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
-                             p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
-                             nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
-                             nullptr, nullptr, nullptr, st));
-    SS_HIP(launch_shadow_query(s->mean, p->n, p->nv, p->at<SunCam>(L.suncam), D,
-                               p->st.sun_map_size, v->b_z, p->st.esm_c, p->st.esm_bias, vis, st));
+    {
+        StageScope scope(p, SS_STAGE_SUN_RASTER, st);
+        SS_HIP(launch_raster_fwd(p->st.tile_size, true, false, p->tiles_sun, p->nv,
+                                 p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
+                                 p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
+                                 nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
+                                 nullptr, nullptr, nullptr, counters + 4, st));
+    }
+    {
+        StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);
+        SS_HIP(launch_shadow_query(s->mean, p->n, p->nv, p->at<SunCam>(L.suncam), D,
+                                   p->st.sun_map_size, v->b_z, p->st.esm_c, p->st.esm_bias, vis,
+                                   st));
+    }
     p->order_sun = order;
     p->sun_valid = true;
     return SS_OK;
@@ -607,6 +688,56 @@ ss_status ss_debug_sun_cameras(ss_plan *p, double *out, ss_stream stream)
         out[9 * v + 7] = c[v].b[1];
         out[9 * v + 8] = c[v].zfar;
     }
+    return SS_OK;
+}
+
+static const char *kStageNames[SS_NUM_STAGES] = {
+    "depth_sort", "project", "bin", "raster_fwd", "raster_bwd", "project_bwd", "reduce",
+    "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query"};
+
+const char *ss_stage_name(int32_t stage)
+{
+    return (stage >= 0 && stage < SS_NUM_STAGES) ? kStageNames[stage] : "";
+}
+
+ss_status ss_plan_set_timing(ss_plan *p, int32_t enable)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    p->timer.on = enable != 0;
+    return SS_OK;
+}
+
+ss_status ss_plan_read_timing(ss_plan *p, double *ms, int64_t *launches)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    StageTimer &t = p->timer;
+    if (!t.pending.empty()) SS_HIP(hipEventSynchronize(t.pending.back().b));
+    for (const auto &q : t.pending) {
+        float e = 0.f;
+        SS_HIP(hipEventElapsedTime(&e, q.a, q.b));
+        t.ms[q.stage] += e;
+        t.count[q.stage] += 1;
+    }
+    t.pending.clear();
+    t.used = 0;
+    for (int k = 0; k < SS_NUM_STAGES; ++k) {
+        if (ms) ms[k] = t.ms[k];
+        if (launches) launches[k] = t.count[k];
+        t.ms[k] = 0.0;
+        t.count[k] = 0;
+    }
+    return SS_OK;
+}
+
+ss_status ss_plan_stats(ss_plan *p, int64_t *out, ss_stream stream)
+{
+    if (!p || !p->ws || !out) return fail(SS_ERR_INVALID_ARG, "plan/workspace/out missing");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long c[6];
+    SS_HIP(hipMemcpyAsync(c, p->at<void>(p->L.counters), sizeof c, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipStreamSynchronize(st));
+    const int map[6] = {0, 2, 3, 1, 4, 5};
+    for (int k = 0; k < 6; ++k) out[k] = (int64_t)c[map[k]];
     return SS_OK;
 }
 

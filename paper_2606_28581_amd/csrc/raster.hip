@@ -316,7 +316,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
     const float *__restrict__ amb, const SunCam *__restrict__ sun, float *__restrict__ image,
     float *__restrict__ Aout, float *__restrict__ Vout, float *__restrict__ Dout,
-    float *__restrict__ Nout, float *__restrict__ Tout, int32_t *__restrict__ lastout)
+    float *__restrict__ Nout, float *__restrict__ Tout, int32_t *__restrict__ lastout,
+    unsigned long long *__restrict__ stats)
 {
     constexpr int NT = TS * TS;
     constexpr int NV4 = DEPTH_ONLY ? 4 : kRecVec4;
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
     const float4 *recv = rec + (size_t)v * (size_t)n * kRecVec4;
     float Tr = 1.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, aV = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
-    int lastpos = 0;
+    int lastpos = 0, ncontrib = 0, neval = 0;
     bool done = !inside;
     const int batch = rc.batch;
     for (uint32_t b0 = start; b0 < end; b0 += batch) {
@@ -353,6 +354,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                 const float4 r0 = R[0];
                 if (!box_hits(r0.x, r0.y, wx0, wy0)) continue;
                 if (done) continue;
+                ++neval;
                 const float4 r1 = R[1], r2 = R[2], r3 = R[3];
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 if (e.alpha >= rc.alpha_min) {
@@ -375,11 +377,24 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                         }
                         Tr = Tn;
                         lastpos = (int)(b0 - start) + j + 1;
+                        ++ncontrib;
                     }
                 }
             }
         }
         if (!__syncthreads_or(!done)) break;
+    }
+    {
+        // work counters: one 64-bit atomic per wave and counter
+        unsigned long long c = (unsigned long long)ncontrib, e = (unsigned long long)neval;
+        for (int d = 32; d > 0; d >>= 1) {
+            c += __shfl_xor(c, d, 64);
+            e += __shfl_xor(e, d, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(stats, c);
+            atomicAdd(stats + 1, e);
+        }
     }
     if (!inside) return;
     const int64_t P = (int64_t)vd.W * vd.H;
@@ -415,11 +430,11 @@ static void launch_fwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const float *rec, int64_t n, const RasterConsts &rc,
                          const float *colC, const float *colc, const float *amb,
                          const SunCam *sun, float *image, float *A, float *V, float *D,
-                         float *N, float *T, int32_t *last)
+                         float *N, float *T, int32_t *last, unsigned long long *stats)
 {
     hipLaunchKernelGGL((k_raster_fwd<TS, DO, HV>), grid, dim3(TS * TS), lds, st, nv, views,
                        ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
-                       amb, sun, image, A, V, D, N, T, last);
+                       amb, sun, image, A, V, D, N, T, last, stats);
 }
 
 hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
@@ -428,7 +443,7 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
                              const RasterConsts &rc, const float *colC, const float *colc,
                              const float *amb, const SunCam *sun, float *image, float *A,
                              float *V, float *D, float *N, float *T, int32_t *last,
-                             hipStream_t st)
+                             unsigned long long *stats, hipStream_t st)
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
@@ -437,13 +452,13 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
     if (ts == TS_) {                                                                             \
         if (depth_only)                                                                          \
             launch_fwd_t<TS_, true, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
-                                           colC, colc, amb, sun, image, A, V, D, N, T, last);    \
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats);\
         else if (has_vis)                                                                        \
             launch_fwd_t<TS_, false, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
-                                           colC, colc, amb, sun, image, A, V, D, N, T, last);    \
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats);\
         else                                                                                     \
             launch_fwd_t<TS_, false, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,  \
-                                            colC, colc, amb, sun, image, A, V, D, N, T, last);   \
+                                            colC, colc, amb, sun, image, A, V, D, N, T, last, stats);\
     }
     SS_FWD(8) else SS_FWD(16) else SS_FWD(32) else return hipErrorInvalidValue;
 #undef SS_FWD

@@ -110,7 +110,7 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
                              const RasterConsts &rc, const float *colC, const float *colc,
                              const float *amb, const SunCam *sun, float *image, float *A,
                              float *V, float *D, float *N, float *T, int32_t *last,
-                             hipStream_t st);
+                             unsigned long long *stats, hipStream_t st);
 hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
                              const ViewDesc *views, const uint32_t *ranges,
                              const uint32_t *lists, const float *rec, int64_t n,

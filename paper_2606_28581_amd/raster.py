@@ -243,6 +243,23 @@ class Plan:
             out["records"] = rec.cpu().numpy()
         return out
 
+    def set_timing(self, on: bool = True):
+        call("ss_plan_set_timing", self.handle, 1 if on else 0)
+
+    def read_timing(self):
+        """{stage: (total ms, launches)} since the last read (blocks)."""
+        ms = (C.c_double * _lib.SS_NUM_STAGES)()
+        cnt = (C.c_int64 * _lib.SS_NUM_STAGES)()
+        call("ss_plan_read_timing", self.handle, C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p))
+        lib = _lib.load()
+        return {lib.ss_stage_name(k).decode(): (ms[k], cnt[k]) for k in range(_lib.SS_NUM_STAGES)}
+
+    def stats(self):
+        out = (C.c_int64 * 6)()
+        call("ss_plan_stats", self.handle, C.cast(out, C.c_void_p), _stream())
+        keys = ("pairs", "contrib", "evaluated", "sun_pairs", "sun_contrib", "sun_evaluated")
+        return dict(zip(keys, list(out)))
+
     def debug_sun_cameras(self):
         nv = len(self.width)
         buf = (C.c_double * (9 * nv))()
