@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="eager steps instead of a HIP graph")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=1024)
     return ap.parse_args()
 
@@ -121,23 +123,29 @@ def main():
     S = settings.sun_map_size
     log(f"[bench] pairs main {K}, sun {Ks}, pixels {P}, workspace {plan.workspace.numel() / 2**30:.1f} GiB")
     dev = "cuda:0"
-    f = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=dev)
-    out = dict(image=f(3 * P), albedo=f(3 * P), vis=f(P), depth=f(P), normal=f(3 * P), T=f(P),
-               last=torch.empty(P, dtype=torch.int32, device=dev))
-    grads = dict(mean=f(N, 3), t_u=f(N, 3), t_v=f(N, 3), scale=f(N, 2), opacity=f(N),
-                 albedo=f(N, 3), dF=f(V, 2, 4), colC=f(V, 3, 3), colc=f(V, 3), ambient=f(V, 3))
     gen = torch.Generator(device=dev)
     gen.manual_seed(spec.seed)
     dI = torch.randn(3 * P, generator=gen, device=dev)
     dD = torch.randn(P, generator=gen, device=dev)
     dN = torch.randn(3 * P, generator=gen, device=dev)
-    vis = f(V, N) if has_sun else None
+    bufs = ss.StepBuffers(N, views.width, views.height, device=dev, with_sun=has_sun,
+                          upstream=(dI, dD, dN))
+    tune = None
+    if not args.no_autotune:
+        t0 = time.time()
+        best, best_ms, table = ss.autotune(plan, surf, views, bufs, reps=2)
+        tune = dict(tile=best.tile_size, batch_depth=best.batch_depth, ms=round(best_ms, 3),
+                    table=[[int(a), int(b), round(c, 3)] for a, b, c in table])
+        log(f"[bench] autotune in {time.time() - t0:.1f} s: tile {best.tile_size}, batch "
+            f"{best.batch_depth}, {best_ms:.2f} ms/step")
+        K, Ks = plan.ensure_capacity(surf, views)
+    graph = None if args.no_graph else ss.Graph(plan, surf, views, bufs)
 
     def step():
-        if has_sun:
-            plan.shadow(surf, views, vis_out=vis, check=False)
-        plan.forward(surf, views, vis, out=out, check=False)
-        plan.backward(surf, views, out, dI, dD, dN, vis=vis, grads=grads)
+        if graph is not None:
+            graph.launch()
+        else:
+            ss.step(plan, surf, views, bufs)
 
     for i in range(args.warmup):
         step()
@@ -161,7 +169,7 @@ def main():
     plan.read_timing()
     plan.set_timing(True)
     for i in range(args.steps):
-        step()
+        ss.step(plan, surf, views, bufs)      # same kernels, eager so events can be recorded
     torch.cuda.synchronize()
     stages = plan.read_timing()
     plan.set_timing(False)
@@ -202,7 +210,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": spec.name, "surfels": N, "views": V, "pixels": P,
-                   "sun_map": S if has_sun else 0, "tile": args.tile, "batch_depth": args.batch,
+                   "sun_map": S if has_sun else 0, "tile": plan.settings.tile_size,
+                   "batch_depth": plan.settings.batch_depth,
+                   "launch": "hipGraph" if graph is not None else "eager",
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "step_hbm": dict(algorithmic_bytes=step_bytes,
@@ -215,6 +225,7 @@ def main():
         "work": dict(pairs=stats["pairs"], contributing=C, evaluated=stats["evaluated"],
                      sun_pairs=stats["sun_pairs"], sun_contributing=stats["sun_contrib"]),
         "kernels": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
+        "autotune": tune,
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")

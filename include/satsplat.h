@@ -211,6 +211,48 @@ ss_status ss_debug_binning(ss_plan *plan, int32_t which, uint32_t *order,
  * b_sun (2), z_far (host memory; blocks on stream). */
 ss_status ss_debug_sun_cameras(ss_plan *plan, double *out, ss_stream stream);
 
+/* ------------------------------------------------------- batched step / graph
+ * One training-step pass over all views: the shadow pass (when views->sun != NULL; it
+ * writes io->vis) then the forward with io->vis as the visibility channel, then the
+ * backward with the given upstream gradients.  All buffers as in ss_forward,
+ * ss_backward and ss_shadow_plain; vis may be NULL only when views->sun is NULL. */
+typedef struct ss_step_io {
+    uint32_t struct_size;       /* sizeof(ss_step_io)                                    */
+    float   *vis;               /* [n_views, n]                                          */
+    float   *sun_depth;         /* [n_views, S, S] or NULL (then kept in the workspace)  */
+    float   *image, *albedo_out, *vis_out, *depth, *normal, *T_final;
+    int32_t *last;
+    const float *d_image, *d_depth, *d_normal;          /* each may be NULL              */
+    float   *d_mean, *d_t_u, *d_t_v, *d_scale, *d_opacity, *d_albedo;
+    float   *d_dF, *d_colC, *d_colc, *d_ambient;
+} ss_step_io;
+
+typedef struct ss_graph ss_graph;
+
+ss_status ss_step(ss_plan *plan, const ss_surfels *s, const ss_views *v, const ss_step_io *io,
+                  ss_stream stream);
+
+/* Capture ss_step with these exact pointers into a HIP graph (no host synchronisation
+ * and no memset nodes inside; grids are sized by the bound pair capacities, counts stay
+ * on the device).  Replays read the current contents of all input buffers.  After a
+ * replay, ss_plan_check reports whether the data needed more pairs than bound; then
+ * rebind a larger workspace and rebuild the graph.  The plan's settings and workspace
+ * must not change while the graph exists. */
+ss_status ss_graph_build(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                         const ss_step_io *io, ss_graph **out);
+ss_status ss_graph_launch(ss_graph *graph, ss_stream stream);
+ss_status ss_graph_destroy(ss_graph *graph);
+
+/* Autotuner: times ss_step (median of `reps` runs after one warm run, HIP events) for
+ * tile_size in {8, 16, 32} x batch_depth in {32, 64, 128, 256} and leaves the plan on
+ * the fastest; *best receives those settings, best_ms its step time.  Candidates whose
+ * pairs exceed the bound capacities are skipped (bind capacities counted with
+ * tile_size 8, the largest pair count, to try all).  table (host, may be NULL) receives
+ * 12 x 3 doubles: tile, batch, ms (ms < 0: skipped). */
+ss_status ss_autotune(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                      const ss_step_io *io, int32_t reps, ss_raster_settings *best,
+                      double *best_ms, double *table, ss_stream stream);
+
 /* ------------------------------------------------------------ measurement
  * Stage timing: when enabled, the library records a HIP event pair on the call's
  * stream around each stage below; ss_plan_read_timing blocks until the recorded

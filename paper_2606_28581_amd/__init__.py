@@ -6,6 +6,6 @@ PyTorch supplies device memory and streams only.  There is no CPU fallback: if
 libsatsplat.so is missing, loading raises.
 """
 from ._lib import SatSplatError, load  # noqa: F401
-from .raster import (Context, Plan, RasterizeAffine2DGS, SurfelTensors, ViewTensors,  # noqa: F401
-                     default_settings, rasterize)
+from .raster import (Context, Graph, Plan, RasterizeAffine2DGS, StepBuffers,  # noqa: F401
+                     SurfelTensors, ViewTensors, autotune, default_settings, rasterize, step)
 from .scene_io import scene_to_device  # noqa: F401

@@ -40,6 +40,17 @@ class Views(C.Structure):
                 ("sun", C.c_void_p), ("b_z", C.c_float)]
 
 
+class StepIO(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("vis", C.c_void_p), ("sun_depth", C.c_void_p),
+                ("image", C.c_void_p), ("albedo_out", C.c_void_p), ("vis_out", C.c_void_p),
+                ("depth", C.c_void_p), ("normal", C.c_void_p), ("T_final", C.c_void_p),
+                ("last", C.c_void_p), ("d_image", C.c_void_p), ("d_depth", C.c_void_p),
+                ("d_normal", C.c_void_p), ("d_mean", C.c_void_p), ("d_t_u", C.c_void_p),
+                ("d_t_v", C.c_void_p), ("d_scale", C.c_void_p), ("d_opacity", C.c_void_p),
+                ("d_albedo", C.c_void_p), ("d_dF", C.c_void_p), ("d_colC", C.c_void_p),
+                ("d_colc", C.c_void_p), ("d_ambient", C.c_void_p)]
+
+
 _P = C.c_void_p
 _I64P = C.POINTER(C.c_int64)
 _SIGS = {
@@ -67,6 +78,14 @@ _SIGS = {
     "ss_plan_read_timing": (C.c_int32, [_P, _P, _P]),
     "ss_stage_name": (C.c_char_p, [C.c_int32]),
     "ss_plan_stats": (C.c_int32, [_P, _P, _P]),
+    "ss_step": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), C.POINTER(StepIO), _P]),
+    "ss_graph_build": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), C.POINTER(StepIO),
+                                   C.POINTER(_P)]),
+    "ss_graph_launch": (C.c_int32, [_P, _P]),
+    "ss_graph_destroy": (C.c_int32, [_P]),
+    "ss_autotune": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), C.POINTER(StepIO),
+                                C.c_int32, C.POINTER(RasterSettings), C.POINTER(C.c_double),
+                                _P, _P]),
 }
 
 SS_NUM_STAGES = 12

@@ -691,6 +691,167 @@ ss_status ss_debug_sun_cameras(ss_plan *p, double *out, ss_stream stream)
     return SS_OK;
 }
 
+// ----------------------------------------------------------- step / graph / tune
+struct ss_graph {
+    ss_plan *plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static ss_status check_io(const ss_plan *p, const ss_views *v, const ss_step_io *io)
+{
+    if (!io || io->struct_size != sizeof(ss_step_io)) return fail(SS_ERR_INVALID_ARG, "bad ss_step_io");
+    if (v && v->sun && !io->vis) return fail(SS_ERR_INVALID_ARG, "io->vis is required with views->sun");
+    (void)p;
+    return SS_OK;
+}
+
+ss_status ss_step(ss_plan *p, const ss_surfels *s, const ss_views *v, const ss_step_io *io,
+                  ss_stream stream)
+{
+    ss_status e = check_io(p, v, io);
+    if (e != SS_OK) return e;
+    if (v && v->sun) {
+        e = ss_shadow_plain(p, s, v, io->sun_depth, io->vis, stream);
+        if (e != SS_OK) return e;
+    }
+    e = ss_forward(p, s, v, io->vis, io->image, io->albedo_out, io->vis_out, io->depth,
+                   io->normal, io->T_final, io->last, stream);
+    if (e != SS_OK) return e;
+    return ss_backward(p, s, v, io->vis, io->albedo_out, io->vis_out, io->T_final, io->last,
+                       io->d_image, io->d_depth, io->d_normal, io->d_mean, io->d_t_u, io->d_t_v,
+                       io->d_scale, io->d_opacity, io->d_albedo, io->d_dF, io->d_colC, io->d_colc,
+                       io->d_ambient, stream);
+}
+
+ss_status ss_graph_build(ss_plan *p, const ss_surfels *s, const ss_views *v, const ss_step_io *io,
+                         ss_graph **out)
+{
+    if (!out) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if ((e = check_io(p, v, io)) != SS_OK) return e;
+    hipStream_t cs = nullptr;
+    SS_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool timing = p->timer.on;
+    p->timer.on = false;
+    hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) {
+        p->timer.on = timing;
+        (void)hipStreamDestroy(cs);
+        return fail(SS_ERR_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(he));
+    }
+    e = ss_step(p, s, v, io, reinterpret_cast<ss_stream>(cs));
+    hipGraph_t g = nullptr;
+    he = hipStreamEndCapture(cs, &g);
+    p->timer.on = timing;
+    (void)hipStreamDestroy(cs);
+    if (e != SS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    if (he != hipSuccess || !g)
+        return fail(SS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(he));
+    hipGraphExec_t x = nullptr;
+    he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(SS_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(he));
+    }
+    auto *G = new ss_graph;
+    G->plan = p;
+    G->graph = g;
+    G->exec = x;
+    *out = G;
+    return SS_OK;
+}
+
+ss_status ss_graph_launch(ss_graph *G, ss_stream stream)
+{
+    if (!G || !G->exec) return fail(SS_ERR_INVALID_ARG, "graph is NULL");
+    SS_HIP(hipSetDevice(G->plan->ctx->device));
+    SS_HIP(hipGraphLaunch(G->exec, reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
+ss_status ss_graph_destroy(ss_graph *G)
+{
+    if (!G) return SS_OK;
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return SS_OK;
+}
+
+ss_status ss_autotune(ss_plan *p, const ss_surfels *s, const ss_views *v, const ss_step_io *io,
+                      int32_t reps, ss_raster_settings *best, double *best_ms, double *table,
+                      ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if ((e = check_io(p, v, io)) != SS_OK) return e;
+    if (reps < 1) reps = 1;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const ss_raster_settings base = p->st;
+    const int tiles[3] = {8, 16, 32};
+    const int batches[4] = {32, 64, 128, 256};
+    hipEvent_t a = nullptr, b = nullptr;
+    SS_HIP(hipEventCreate(&a));
+    SS_HIP(hipEventCreate(&b));
+    double best_t = -1.0;
+    ss_raster_settings best_s = base;
+    int row = 0;
+    for (int ti = 0; ti < 3; ++ti) {
+        for (int bi = 0; bi < 4; ++bi, ++row) {
+            ss_raster_settings c = base;
+            c.tile_size = tiles[ti];
+            c.batch_depth = batches[bi];
+            double ms = -1.0;
+            if ((e = ss_plan_set_settings(p, &c)) != SS_OK) break;
+            int64_t km = 0, ks = 0;
+            if ((e = ss_count_pairs(p, s, v, &km, &ks, stream)) != SS_OK) break;
+            if (km <= p->cap_main && ks <= p->cap_sun) {
+                if ((e = ss_step(p, s, v, io, stream)) != SS_OK) break;
+                std::vector<double> t;
+                for (int r = 0; r < reps; ++r) {
+                    SS_HIP(hipEventRecord(a, st));
+                    if ((e = ss_step(p, s, v, io, stream)) != SS_OK) break;
+                    SS_HIP(hipEventRecord(b, st));
+                    SS_HIP(hipEventSynchronize(b));
+                    float f = 0.f;
+                    SS_HIP(hipEventElapsedTime(&f, a, b));
+                    t.push_back(f);
+                }
+                if (e != SS_OK) break;
+                std::sort(t.begin(), t.end());
+                ms = t[t.size() / 2];
+                if (best_t < 0 || ms < best_t) { best_t = ms; best_s = c; }
+            }
+            if (table) {
+                table[3 * row] = c.tile_size;
+                table[3 * row + 1] = c.batch_depth;
+                table[3 * row + 2] = ms;
+            }
+        }
+        if (e != SS_OK) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != SS_OK) {
+        (void)ss_plan_set_settings(p, &base);
+        return e;
+    }
+    if (best_t < 0) {
+        (void)ss_plan_set_settings(p, &base);
+        return fail(SS_ERR_CAPACITY, "no candidate fits the bound pair capacities");
+    }
+    if ((e = ss_plan_set_settings(p, &best_s)) != SS_OK) return e;
+    if (best) *best = best_s;
+    if (best_ms) *best_ms = best_t;
+    return SS_OK;
+}
+
 static const char *kStageNames[SS_NUM_STAGES] = {
     "depth_sort", "project", "bin", "raster_fwd", "raster_bwd", "project_bwd", "reduce",
     "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query"};

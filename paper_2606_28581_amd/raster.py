@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import RasterSettings, Surfels, Views, call
+from ._lib import RasterSettings, StepIO, Surfels, Views, call
 
 
 def default_settings(**overrides) -> RasterSettings:
@@ -265,6 +265,82 @@ class Plan:
         buf = (C.c_double * (9 * nv))()
         call("ss_debug_sun_cameras", self.handle, C.cast(buf, C.c_void_p), _stream())
         return np.frombuffer(buf, dtype=np.float64).reshape(nv, 9).copy()
+
+
+class StepBuffers:
+    """Every device buffer one whole step (shadow pass, forward, backward) touches."""
+
+    def __init__(self, n: int, width, height, device="cuda:0", with_sun=True, sun_map=1024,
+                 upstream=None):
+        P = int(np.sum(np.asarray(width, np.int64) * np.asarray(height, np.int64)))
+        nv = len(width)
+        f = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=device)
+        self.vis = f(nv, n) if with_sun else None
+        self.sun_depth = None
+        self.out = dict(image=f(3 * P), albedo=f(3 * P), vis=f(P), depth=f(P), normal=f(3 * P),
+                        T=f(P), last=torch.empty(P, dtype=torch.int32, device=device))
+        self.grads = dict(mean=f(n, 3), t_u=f(n, 3), t_v=f(n, 3), scale=f(n, 2), opacity=f(n),
+                          albedo=f(n, 3), dF=f(nv, 2, 4), colC=f(nv, 3, 3), colc=f(nv, 3),
+                          ambient=f(nv, 3))
+        self.upstream = upstream or (None, None, None)
+
+    def c(self) -> StepIO:
+        o, g = self.out, self.grads
+        dI, dD, dN = self.upstream
+        io = StepIO()
+        io.struct_size = C.sizeof(StepIO)
+        vals = dict(vis=self.vis, sun_depth=self.sun_depth, image=o["image"],
+                    albedo_out=o["albedo"], vis_out=o["vis"], depth=o["depth"],
+                    normal=o["normal"], T_final=o["T"], last=o["last"], d_image=dI, d_depth=dD,
+                    d_normal=dN, d_mean=g["mean"], d_t_u=g["t_u"], d_t_v=g["t_v"],
+                    d_scale=g["scale"], d_opacity=g["opacity"], d_albedo=g["albedo"],
+                    d_dF=g["dF"], d_colC=g["colC"], d_colc=g["colc"], d_ambient=g["ambient"])
+        for k, t in vals.items():
+            setattr(io, k, None if t is None else _ptr(t).value)
+        return io
+
+
+class Graph:
+    """A captured whole step (HIP graph) replayed on torch's current stream."""
+
+    def __init__(self, plan: "Plan", s: SurfelTensors, v: ViewTensors, bufs: StepBuffers):
+        h = C.c_void_p()
+        self._keep = (s, v, bufs)
+        sc, vc, io = s.c(), v.c(), bufs.c()
+        call("ss_graph_build", plan.handle, C.byref(sc), C.byref(vc), C.byref(io), C.byref(h))
+        self.handle = h
+
+    def launch(self):
+        call("ss_graph_launch", self.handle, _stream())
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib._lib is not None:
+            _lib._lib.ss_graph_destroy(self.handle)
+            self.handle = None
+
+
+def step(plan: "Plan", s: SurfelTensors, v: ViewTensors, bufs: StepBuffers):
+    sc, vc, io = s.c(), v.c(), bufs.c()
+    call("ss_step", plan.handle, C.byref(sc), C.byref(vc), C.byref(io), _stream())
+
+
+def autotune(plan: "Plan", s: SurfelTensors, v: ViewTensors, bufs: StepBuffers, reps: int = 3):
+    """Bind capacities for the largest pair count (tile 8), time all 12 candidates, leave
+    the plan on the fastest.  Returns (settings, ms, table)."""
+    base = plan.settings
+    probe = default_settings(**{k: getattr(base, k) for k, _ in RasterSettings._fields_
+                                if k != "struct_size"})
+    probe.tile_size = 8
+    plan.set_settings(probe)
+    plan.ensure_capacity(s, v)
+    best = RasterSettings()
+    ms = C.c_double()
+    table = (C.c_double * 36)()
+    sc, vc, io = s.c(), v.c(), bufs.c()
+    call("ss_autotune", plan.handle, C.byref(sc), C.byref(vc), C.byref(io), int(reps),
+         C.byref(best), C.byref(ms), C.cast(table, C.c_void_p), _stream())
+    plan.settings = best
+    return best, ms.value, np.frombuffer(table, dtype=np.float64).reshape(12, 3).copy()
 
 
 class RasterizeAffine2DGS(torch.autograd.Function):
