@@ -253,6 +253,55 @@ ss_status ss_autotune(ss_plan *plan, const ss_surfels *s, const ss_views *v,
                       const ss_step_io *io, int32_t reps, ss_raster_settings *best,
                       double *best_ms, double *table, ss_stream stream);
 
+/* ------------------------------------------------- learned shadow surrogate
+ * Not in the paper: a small MLP that stands in for the geometric shadow pass, trained
+ * on that pass's labels; the geometric pass stays its fallback.  Network: features of
+ * the normalised centre p_hat = fl32(fl32(p - centre) * inv_half), sin and cos of
+ * pi 2^k p_hat_c for k = 0..15 and c = 0..2 (interleaved per frequency, coordinate
+ * major), then cos phi, sin phi, sin theta, cos theta, zero padded to 128;
+ * 128 -> 64 -> 64 -> 64 (ReLU) -> 1.  BF16 weights and activations, FP32 accumulation
+ * on MFMA.  Parameters: one FP32 vector [W1 (64x128, row = output), b1, W2 (64x64),
+ * b2, W3 (64x64), b3, w4 (64), b4] of 16641 floats (caller-owned device memory). */
+typedef struct ss_mlp ss_mlp;
+typedef struct ss_mlp_config {
+    uint32_t struct_size;   /* sizeof(ss_mlp_config)             */
+    float    centre[3];     /* normalisation centre, metres      */
+    float    inv_half;      /* 1 / normalisation half extent, 1/m */
+} ss_mlp_config;
+#define SS_MLP_PARAMS 16641
+
+ss_status ss_mlp_create(ss_context *ctx, const ss_mlp_config *cfg, ss_mlp **out);
+ss_status ss_mlp_destroy(ss_mlp *mlp);
+/* Workspace for training batches of up to max_points (inference needs only the
+ * weight copies, max_points may be 0). */
+ss_status ss_mlp_workspace_size(ss_mlp *mlp, int64_t max_points, size_t *bytes);
+ss_status ss_mlp_bind_workspace(ss_mlp *mlp, void *workspace, size_t bytes, int64_t max_points);
+/* out[i] = logit (or sigmoid(logit) when prob != 0).  all_pairs = 0: point i has
+ * position pts[i] and sun sun[i], M = n_pts = n_sun.  all_pairs = 1: M = n_sun * n_pts,
+ * point i has position pts[i % n_pts] and sun sun[i / n_pts].  pts [n_pts,3],
+ * sun [n_sun,2] (phi, theta) radians. */
+ss_status ss_mlp_forward(ss_mlp *mlp, const float *w, const float *pts, int64_t n_pts,
+                         const float *sun, int64_t n_sun, int32_t all_pairs, int32_t prob,
+                         float *out, ss_stream stream);
+/* Gradient (overwritten, [16641]) of  scale * sum_i L_i  for M <= max_points paired
+ * points, with L_i = BCE-with-logits(logit_i, labels[i]) when labels != NULL, else
+ * L_i = d_logits[i] * logit_i.  loss (device float[1] or NULL) receives
+ * scale * sum_i BCE_i.  Backward rounding: each pre-activation gradient is rounded to
+ * BF16 before it enters a product (same points as the forward's BF16 operands). */
+ss_status ss_mlp_backward(ss_mlp *mlp, const float *w, const float *pts, const float *sun,
+                          int64_t M, const float *labels, const float *d_logits, float scale,
+                          float *d_w, float *loss, ss_stream stream);
+/* Adam on FP32 master weights (step counts from 1). */
+ss_status ss_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr,
+                      float beta1, float beta2, float eps, int32_t step, ss_stream stream);
+/* Surrogate shadow pass: vis[v,k] = sigmoid(MLP(p_k, sun_v)) for every view and surfel;
+ * points with |vis - 0.5| < band fall back to the geometric pass (ss_shadow_plain's
+ * definition), rasterizing only the sun-map tiles their 3x3 windows touch.  Requires
+ * views->sun.  The number of fallback points is reported by ss_plan_stats ([6]). */
+ss_status ss_shadow_surrogate(ss_plan *plan, ss_mlp *mlp, const float *w, const ss_surfels *s,
+                              const ss_views *v, float band, float *vis, float *sun_depth,
+                              ss_stream stream);
+
 /* ------------------------------------------------------------ measurement
  * Stage timing: when enabled, the library records a HIP event pair on the call's
  * stream around each stage below; ss_plan_read_timing blocks until the recorded
@@ -271,15 +320,18 @@ ss_status ss_autotune(ss_plan *plan, const ss_surfels *s, const ss_views *v,
 #define SS_STAGE_SUN_BIN      9
 #define SS_STAGE_SUN_RASTER  10   /* depth-only compositing of the sun maps                */
 #define SS_STAGE_SHADOW_QUERY 11
-#define SS_NUM_STAGES        12
+#define SS_STAGE_MLP         12   /* surrogate MLP inference (weight copy + fused forward)  */
+#define SS_STAGE_FALLBACK_FLAG 13 /* surrogate fallback: flag points and their sun tiles    */
+#define SS_NUM_STAGES        14
 ss_status ss_plan_set_timing(ss_plan *plan, int32_t enable);
 ss_status ss_plan_read_timing(ss_plan *plan, double *ms, int64_t *launches);
 const char *ss_stage_name(int32_t stage);
 
-/* Work counters of the last forward / shadow pass (blocks on stream), host int64[6]:
+/* Work counters of the last forward / shadow pass (blocks on stream), host int64[7]:
  *   [0] pairs bound (tile, surfel) main views   [1] contributing (pixel, surfel) pairs
  *   [2] evaluated (pixel, surfel) pairs after per-wave culling (main views)
- *   [3] pairs bound, sun views   [4] contributing pairs, sun   [5] evaluated pairs, sun */
+ *   [3] pairs bound, sun views   [4] contributing pairs, sun   [5] evaluated pairs, sun
+ *   [6] fallback points of the last surrogate shadow pass */
 ss_status ss_plan_stats(ss_plan *plan, int64_t *out, ss_stream stream);
 
 #ifdef __cplusplus

@@ -51,6 +51,10 @@ class StepIO(C.Structure):
                 ("d_colc", C.c_void_p), ("d_ambient", C.c_void_p)]
 
 
+class MlpConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("centre", C.c_float * 3), ("inv_half", C.c_float)]
+
+
 _P = C.c_void_p
 _I64P = C.POINTER(C.c_int64)
 _SIGS = {
@@ -86,9 +90,21 @@ _SIGS = {
     "ss_autotune": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), C.POINTER(StepIO),
                                 C.c_int32, C.POINTER(RasterSettings), C.POINTER(C.c_double),
                                 _P, _P]),
+    "ss_mlp_create": (C.c_int32, [_P, C.POINTER(MlpConfig), C.POINTER(_P)]),
+    "ss_mlp_destroy": (C.c_int32, [_P]),
+    "ss_mlp_workspace_size": (C.c_int32, [_P, C.c_int64, C.POINTER(C.c_size_t)]),
+    "ss_mlp_bind_workspace": (C.c_int32, [_P, _P, C.c_size_t, C.c_int64]),
+    "ss_mlp_forward": (C.c_int32, [_P, _P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32,
+                                   _P, _P]),
+    "ss_mlp_backward": (C.c_int32, [_P, _P, _P, _P, C.c_int64, _P, _P, C.c_float, _P, _P, _P]),
+    "ss_mlp_adam": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float,
+                                C.c_float, C.c_int32, _P]),
+    "ss_shadow_surrogate": (C.c_int32, [_P, _P, _P, C.POINTER(Surfels), C.POINTER(Views),
+                                        C.c_float, _P, _P, _P]),
 }
 
-SS_NUM_STAGES = 12
+SS_NUM_STAGES = 14
+SS_MLP_PARAMS = 16641
 
 _lib = None
 

@@ -2,6 +2,7 @@
 // and the order in which the kernels of one call run on the caller's stream.
 #include "satsplat.h"
 #include "ss_internal.h"
+#include "ss_mlp.h"
 
 #include <algorithm>
 #include <cmath>
@@ -53,7 +54,7 @@ struct Layout {
     size_t rec_main, tiles_main, counts_main, offs_main, scanparts;
     size_t pk_a, pv_a, pk_b, pv_b, ranges_main, recgrad, colour_parts, dF_parts;
     size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
-    size_t sun_depth, bounds, radix_temp;
+    size_t sun_depth, bounds, radix_temp, tmask_sun;
     size_t total;
 };
 
@@ -199,6 +200,7 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.sun_depth = take(nv * S * S * 4);
     L.bounds = take((size_t)bounds_blocks(p->n) * 6 * 8);
     L.radix_temp = take(radix_temp_bytes(std::max<int64_t>(p->n, std::max(cm, cs))));
+    L.tmask_sun = take((size_t)p->tiles_sun_max * 4);
     L.total = o;
     return L;
 }
@@ -283,7 +285,8 @@ static ss_status prepare(ss_plan *p, const ss_surfels *s, const ss_views *v, boo
 
 // Projection + pair-count scan (+ emission, tile sort and ranges when `bin`).
 static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32_t *order,
-                           const float *sorted, const float *vis, bool bin, hipStream_t st)
+                           const float *sorted, const float *vis, bool bin, hipStream_t st,
+                           const uint32_t *tmask = nullptr)
 {
     const Layout &L = p->L;
     const RasterConsts rc = consts(p->st);
@@ -299,7 +302,7 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
         StageScope scope(p, sun ? SS_STAGE_SUN_PROJECT : SS_STAGE_PROJECT, st);
         SS_HIP(launch_project(sorted, p->n, order, p->nv, views, v->Fxy, sun ? nullptr : v->dF,
                               sun ? p->at<SunCam>(L.suncam) : nullptr, sun ? nullptr : vis,
-                              v->b_z, p->st.tile_size, rc, rec, tiles, counts, st));
+                              v->b_z, p->st.tile_size, rc, rec, tiles, counts, tmask, st));
     }
     StageScope scope(p, sun ? SS_STAGE_SUN_BIN : SS_STAGE_BIN, st);
     SS_HIP(scan_pair_counts(counts, p->n, p->nv, offs, p->at<uint32_t>(L.scanparts), counters,
@@ -307,7 +310,8 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
     if (!bin) return SS_OK;
     uint32_t *ka = p->at<uint32_t>(sun ? L.qk_a : L.pk_a), *va = p->at<uint32_t>(sun ? L.qv_a : L.pv_a);
     uint32_t *kb = p->at<uint32_t>(sun ? L.qk_b : L.pk_b), *vb = p->at<uint32_t>(sun ? L.qv_b : L.pv_b);
-    SS_HIP(launch_emit(order, p->n, p->nv, views, tiles, counts, offs, (uint64_t)cap, ka, va, st));
+    SS_HIP(launch_emit(order, p->n, p->nv, views, tiles, counts, offs, (uint64_t)cap, ka, va, tmask,
+                       st));
     const int32_t ntiles = sun ? p->tiles_sun : p->tiles_main;
     bool in_b = false;
     SS_HIP(radix_sort_pairs(ka, va, kb, vb, cap, counters + (sun ? 1 : 0), 0, bits_for(ntiles),
@@ -331,6 +335,42 @@ static ss_status upload_views(ss_plan *p)
     SS_HIP(hipMemset(p->at<void>(p->L.counters), 0, 16 * sizeof(unsigned long long)));
     SS_HIP(hipMemset(p->at<void>(p->L.flags), 0, 16 * sizeof(uint32_t)));
     return SS_OK;
+}
+
+// ------------------------------------------------------------------ surrogate MLP
+struct ss_mlp {
+    ss_context *ctx = nullptr;
+    ss_mlp_config cfg{};
+    char *ws = nullptr;
+    size_t bytes = 0;
+    int64_t maxp = 0;
+    size_t o_wb = 0, o_wf = 0, o_F = 0, o_H = 0, o_logit = 0, o_dA = 0, o_pdw = 0, o_pdb = 0,
+           o_pout = 0, total = 0;
+    template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+static void mlp_layout(ss_mlp *m, int64_t maxp)
+{
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
+    const size_t M = (size_t)std::max<int64_t>(maxp, 0);
+    const size_t nblk = (size_t)mlp_dw_blocks((int64_t)M);
+    const size_t nout = (M + 255) / 256;
+    m->o_wb = take(kMlpBf16 * 2);
+    m->o_wf = take(kMlpF32 * 4);
+    m->o_F = take(M * kMlpIn * 2);
+    m->o_H = take(3 * M * kMlpWidth * 2);
+    m->o_logit = take(M * 4);
+    m->o_dA = take(2 * M * kMlpWidth * 2);
+    m->o_pdw = take(nblk * kMlpWidth * kMlpIn * 4);
+    m->o_pdb = take(nblk * kMlpWidth * 4);
+    m->o_pout = take(nout * 66 * 4);
+    m->total = o;
+}
+
+static MlpNorm mlp_norm(const ss_mlp *m)
+{
+    return MlpNorm{m->cfg.centre[0], m->cfg.centre[1], m->cfg.centre[2], m->cfg.inv_half};
 }
 
 // ======================================================================= C ABI
@@ -627,7 +667,7 @@ ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, fl
         StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);
         SS_HIP(launch_shadow_query(s->mean, p->n, p->nv, p->at<SunCam>(L.suncam), D,
                                    p->st.sun_map_size, v->b_z, p->st.esm_c, p->st.esm_bias, vis,
-                                   st));
+                                   0.f, st));
     }
     p->order_sun = order;
     p->sun_valid = true;
@@ -852,9 +892,184 @@ ss_status ss_autotune(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
     return SS_OK;
 }
 
+ss_status ss_mlp_create(ss_context *ctx, const ss_mlp_config *cfg, ss_mlp **out)
+{
+    if (!out) return fail(SS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!ctx || !cfg || cfg->struct_size != sizeof(ss_mlp_config))
+        return fail(SS_ERR_INVALID_ARG, "context or config invalid");
+    if (!(cfg->inv_half > 0.f) || !std::isfinite(cfg->inv_half))
+        return fail(SS_ERR_INVALID_ARG, "inv_half must be positive");
+    auto *m = new ss_mlp;
+    m->ctx = ctx;
+    m->cfg = *cfg;
+    *out = m;
+    return SS_OK;
+}
+
+ss_status ss_mlp_destroy(ss_mlp *m)
+{
+    delete m;
+    return SS_OK;
+}
+
+ss_status ss_mlp_workspace_size(ss_mlp *m, int64_t max_points, size_t *bytes)
+{
+    if (!m || !bytes || max_points < 0) return fail(SS_ERR_INVALID_ARG, "bad arguments");
+    ss_mlp tmp;
+    mlp_layout(&tmp, max_points);
+    *bytes = tmp.total;
+    return SS_OK;
+}
+
+ss_status ss_mlp_bind_workspace(ss_mlp *m, void *ws, size_t bytes, int64_t max_points)
+{
+    if (!m || !ws || max_points < 0) return fail(SS_ERR_INVALID_ARG, "bad arguments");
+    if (((uintptr_t)ws & 255) != 0) return fail(SS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    mlp_layout(m, max_points);
+    if (bytes < m->total) return fail(SS_ERR_CAPACITY, "workspace smaller than required");
+    m->ws = reinterpret_cast<char *>(ws);
+    m->bytes = bytes;
+    m->maxp = max_points;
+    return SS_OK;
+}
+
+ss_status ss_mlp_forward(ss_mlp *m, const float *w, const float *pts, int64_t n_pts,
+                         const float *sun, int64_t n_sun, int32_t all_pairs, int32_t prob,
+                         float *out, ss_stream stream)
+{
+    if (!m || !m->ws) return fail(SS_ERR_STATE, "MLP has no workspace");
+    if (!w || !pts || !sun || !out) return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    if (n_pts < 0 || n_sun < 0) return fail(SS_ERR_INVALID_ARG, "negative count");
+    if (!all_pairs && n_pts != n_sun) return fail(SS_ERR_INVALID_ARG, "paired mode needs n_pts == n_sun");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SS_HIP(hipSetDevice(m->ctx->device));
+    SS_HIP(launch_mlp_prep(w, m->at<uint16_t>(m->o_wb), m->at<float>(m->o_wf), st));
+    const int64_t M = all_pairs ? n_pts * n_sun : n_pts;
+    SS_HIP(launch_mlp_forward(m->at<uint16_t>(m->o_wb), m->at<float>(m->o_wf), pts, sun, M,
+                              all_pairs ? n_pts : 0, mlp_norm(m), prob != 0, out, nullptr, nullptr,
+                              st));
+    return SS_OK;
+}
+
+ss_status ss_mlp_backward(ss_mlp *m, const float *w, const float *pts, const float *sun, int64_t M,
+                          const float *labels, const float *d_logits, float scale, float *d_w,
+                          float *loss, ss_stream stream)
+{
+    if (!m || !m->ws) return fail(SS_ERR_STATE, "MLP has no workspace");
+    if (!w || !pts || !sun || !d_w || (!labels && !d_logits))
+        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    if (M < 1 || M > m->maxp) return fail(SS_ERR_CAPACITY, "M must be in [1, max_points]");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SS_HIP(hipSetDevice(m->ctx->device));
+    uint16_t *wb = m->at<uint16_t>(m->o_wb);
+    float *wf = m->at<float>(m->o_wf);
+    uint16_t *F = m->at<uint16_t>(m->o_F);
+    uint16_t *H = m->at<uint16_t>(m->o_H);
+    uint16_t *H1 = H, *H2 = H + M * kMlpWidth, *H3 = H + 2 * M * kMlpWidth;
+    uint16_t *dA0 = m->at<uint16_t>(m->o_dA), *dA1 = dA0 + M * kMlpWidth;
+    float *logit = m->at<float>(m->o_logit);
+    float *pdw = m->at<float>(m->o_pdw), *pdb = m->at<float>(m->o_pdb), *pout = m->at<float>(m->o_pout);
+    const int nblk = mlp_dw_blocks(M);
+    const int nout = (int)((M + 255) / 256);
+    SS_HIP(launch_mlp_prep(w, wb, wf, st));
+    // saved activations: saveH holds h1, h2, h3 contiguous ([3][M][64])
+    SS_HIP(launch_mlp_forward(wb, wf, pts, sun, M, 0, mlp_norm(m), false, logit, F, H, st));
+    SS_HIP(launch_mlp_out_bwd(logit, labels, d_logits, scale, wb, H3, M, dA0, pout, st));
+    SS_HIP(launch_mlp_reduce(pout, nout, kMlpWidth + 1, 66, d_w + kOffW4, st));
+    if (loss) SS_HIP(launch_mlp_reduce(pout + 65, nout, 1, 66, loss, st));
+    // layer 3
+    SS_HIP(launch_mlp_dw(dA0, H2, kMlpWidth, M, pdw, pdb, st));
+    SS_HIP(launch_mlp_reduce(pdw, nblk, kMlpW3, kMlpW3, d_w + kOffW3, st));
+    SS_HIP(launch_mlp_reduce(pdb, nblk, kMlpWidth, kMlpWidth, d_w + kOffB3, st));
+    SS_HIP(launch_mlp_dh(dA0, wb + kMlpW1 + kMlpW2, H2, M, dA1, st));
+    // layer 2
+    SS_HIP(launch_mlp_dw(dA1, H1, kMlpWidth, M, pdw, pdb, st));
+    SS_HIP(launch_mlp_reduce(pdw, nblk, kMlpW2, kMlpW2, d_w + kOffW2, st));
+    SS_HIP(launch_mlp_reduce(pdb, nblk, kMlpWidth, kMlpWidth, d_w + kOffB2, st));
+    SS_HIP(launch_mlp_dh(dA1, wb + kMlpW1, H1, M, dA0, st));
+    // layer 1
+    SS_HIP(launch_mlp_dw(dA0, F, kMlpIn, M, pdw, pdb, st));
+    SS_HIP(launch_mlp_reduce(pdw, nblk, kMlpW1, kMlpW1, d_w + kOffW1, st));
+    SS_HIP(launch_mlp_reduce(pdb, nblk, kMlpWidth, kMlpWidth, d_w + kOffB1, st));
+    return SS_OK;
+}
+
+ss_status ss_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,
+                      float beta2, float eps, int32_t step, ss_stream stream)
+{
+    if (!w || !m || !v || !g || n < 0 || step < 1) return fail(SS_ERR_INVALID_ARG, "bad arguments");
+    SS_HIP(launch_mlp_adam(w, m, v, g, n, lr, beta1, beta2, eps, step,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
+ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_surfels *s,
+                              const ss_views *v, float band, float *vis, float *sun_depth,
+                              ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!mlp || !mlp->ws) return fail(SS_ERR_STATE, "MLP has no workspace");
+    if (!v->sun || !vis || !w) return fail(SS_ERR_INVALID_ARG, "views.sun, vis and w are required");
+    if (!(band >= 0.f && band <= 0.5f)) return fail(SS_ERR_INVALID_ARG, "band must be in [0, 0.5]");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Layout &L = p->L;
+    p->sun_valid = false;
+    unsigned long long *counters = p->at<unsigned long long>(L.counters);
+    SS_HIP(fill_u32(p->at<uint32_t>(L.flags) + 1, 0u, 1, st));
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 4), 0u, 6, st));
+    {
+        StageScope scope(p, SS_STAGE_MLP, st);
+        SS_HIP(launch_mlp_prep(w, mlp->at<uint16_t>(mlp->o_wb), mlp->at<float>(mlp->o_wf), st));
+        SS_HIP(launch_mlp_forward(mlp->at<uint16_t>(mlp->o_wb), mlp->at<float>(mlp->o_wf), s->mean,
+                                  v->sun, p->n * (int64_t)p->nv, p->n, mlp_norm(mlp), true, vis,
+                                  nullptr, nullptr, st));
+    }
+    uint32_t *order;
+    float *sorted;
+    if ((e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
+    {
+        StageScope scope(p, SS_STAGE_SUN_CAMERA, st);
+        SS_HIP(launch_sun_cameras(s->mean, p->n, p->nv, v->Fxy, v->dF, v->sun, v->b_z,
+                                  p->st.sun_map_size, p->at<double>(L.bounds),
+                                  p->at<SunCam>(L.suncam), st));
+    }
+    uint32_t *tmask = p->at<uint32_t>(L.tmask_sun);
+    {
+        StageScope scope(p, SS_STAGE_FALLBACK_FLAG, st);
+        SS_HIP(fill_u32(tmask, 0u, p->tiles_sun, st));
+        SS_HIP(launch_flag_tiles(s->mean, p->n, p->nv, p->at<SunCam>(L.suncam),
+                                 p->at<ViewDesc>(L.views_sun), p->st.sun_map_size, p->st.tile_size,
+                                 vis, band, tmask, counters + 6, st));
+    }
+    if ((e = bin_views(p, v, true, order, sorted, nullptr, true, st, tmask)) != SS_OK) return e;
+    float *D = sun_depth ? sun_depth : p->at<float>(L.sun_depth);
+    const RasterConsts rc = consts(p->st);
+    {
+        StageScope scope(p, SS_STAGE_SUN_RASTER, st);
+        SS_HIP(launch_raster_fwd(p->st.tile_size, true, false, p->tiles_sun, p->nv,
+                                 p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
+                                 p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
+                                 nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
+                                 nullptr, nullptr, nullptr, counters + 4, st));
+    }
+    {
+        StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);
+        if (band > 0.f)
+            SS_HIP(launch_shadow_query(s->mean, p->n, p->nv, p->at<SunCam>(L.suncam), D,
+                                       p->st.sun_map_size, v->b_z, p->st.esm_c, p->st.esm_bias, vis,
+                                       band, st));
+    }
+    p->order_sun = order;
+    p->sun_valid = true;
+    return SS_OK;
+}
+
 static const char *kStageNames[SS_NUM_STAGES] = {
     "depth_sort", "project", "bin", "raster_fwd", "raster_bwd", "project_bwd", "reduce",
-    "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query"};
+    "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query", "mlp_forward",
+    "fallback_flag"};
 
 const char *ss_stage_name(int32_t stage)
 {
@@ -894,11 +1109,11 @@ ss_status ss_plan_stats(ss_plan *p, int64_t *out, ss_stream stream)
 {
     if (!p || !p->ws || !out) return fail(SS_ERR_INVALID_ARG, "plan/workspace/out missing");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    unsigned long long c[6];
+    unsigned long long c[7];
     SS_HIP(hipMemcpyAsync(c, p->at<void>(p->L.counters), sizeof c, hipMemcpyDeviceToHost, st));
     SS_HIP(hipStreamSynchronize(st));
-    const int map[6] = {0, 2, 3, 1, 4, 5};
-    for (int k = 0; k < 6; ++k) out[k] = (int64_t)c[map[k]];
+    const int map[7] = {0, 2, 3, 1, 4, 5, 6};
+    for (int k = 0; k < 7; ++k) out[k] = (int64_t)c[map[k]];
     return SS_OK;
 }
 

@@ -1,0 +1,562 @@
+// Learned sun-visibility surrogate on gfx950 MFMA (not in the paper; a stand-in for the
+// geometric shadow pass of Sec. 3.1 / 3.3, trained on that pass's labels).
+//
+// Network: Fourier features of the normalised surfel centre (16 frequencies x sin/cos
+// x 3 coordinates) + (cos phi, sin phi, sin theta, cos theta) padded to 128, then
+// 128 -> 64 -> 64 -> 64 (ReLU) -> 1.  BF16 weights and activations, FP32 accumulation
+// with v_mfma_f32_16x16x32_bf16.  Parameters are one FP32 master vector
+// [W1 (64x128), b1, W2 (64x64), b2, W3 (64x64), b3, w4 (64), b4].
+//
+// Forward: one wave owns 32 points (two 16-row MFMA tiles).  Each lane computes exactly
+// the 8 features its A operand needs (point l%16, features 32 ks + 8 (l/16) .. +7), so
+// the 96 sin/cos values of a point are spread over 4 lanes with no duplication and no
+// LDS staging.  Hidden activations go through a small per-wave LDS tile to move from the
+// accumulator layout (4 points x 1 neuron per lane) to the operand layout (1 point x 8
+// neurons per lane).  Weights live in LDS, row-major [out][in], so a B operand is 16
+// contiguous bytes.
+#include "ss_internal.h"
+#include "ss_mlp.h"
+
+namespace ss {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16;
+
+constexpr int kPtsPerWave = 32;
+constexpr int kMlpThreads = 256;
+constexpr int kMlpWaves = kMlpThreads / 64;
+constexpr int kHStride = 72;        // bf16 row stride of the per-wave activation tile
+
+__device__ __forceinline__ u16 f2bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((uint32_t)b << 16); }
+
+union Frag {
+    bf16x8 v;
+    u16 h[8];
+    uint4 q;
+};
+
+__device__ __forceinline__ f32x4 mfma(const Frag &a, const Frag &b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
+}
+
+// --------------------------------------------------------------- weight prep
+// FP32 master -> BF16 copies (W1, W2, W3, w4) and FP32 biases, in the MLP workspace.
+__global__ void k_mlp_prep(const float *__restrict__ w, u16 *__restrict__ wb, float *__restrict__ wf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMlpW1 + kMlpW2 + kMlpW3 + kMlpWidth) {
+        int src;
+        if (i < kMlpW1) src = kOffW1 + i;
+        else if (i < kMlpW1 + kMlpW2) src = kOffW2 + (i - kMlpW1);
+        else if (i < kMlpW1 + kMlpW2 + kMlpW3) src = kOffW3 + (i - kMlpW1 - kMlpW2);
+        else src = kOffW4 + (i - kMlpW1 - kMlpW2 - kMlpW3);
+        wb[i] = f2bf(w[src]);
+    }
+    if (i < 3 * kMlpWidth + 1) {
+        int src = i < 64 ? kOffB1 + i : i < 128 ? kOffB2 + i - 64 : i < 192 ? kOffB3 + i - 128 : kOffB4;
+        wf[i] = w[src];
+    }
+}
+
+// Feature chunk of one lane: point p_hat (3) and sun (phi, theta) -> 8 bf16 values for
+// the k-step ks and lane group g (features 32 ks + 8 g .. + 7).
+__device__ __forceinline__ void feature_chunk(const float ph[3], float cphi, float sphi,
+                                              float sth, float cth, int ks, int g, Frag &out)
+{
+    if (ks < 3) {
+        const float x0 = ph[ks];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * g + q;                       // frequency
+            const float x = x0 * (float)(1u << k);        // exact: power-of-two scaling
+            const float r = x - 2.f * rintf(0.5f * x);    // exact reduction to [-1, 1]
+            float s, c;
+            sincospif(r, &s, &c);
+            out.h[2 * q] = f2bf(s);
+            out.h[2 * q + 1] = f2bf(c);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) out.h[e] = 0;
+        if (g == 0) {
+            out.h[0] = f2bf(cphi); out.h[1] = f2bf(sphi);
+            out.h[2] = f2bf(sth);  out.h[3] = f2bf(cth);
+        }
+    }
+}
+
+struct MlpLds {
+    u16 W1[kMlpWidth * kMlpIn];
+    u16 W2[kMlpWidth * kMlpWidth];
+    u16 W3[kMlpWidth * kMlpWidth];
+    float w4[kMlpWidth];
+    float b[3 * kMlpWidth + 1];
+    u16 H[kMlpWaves][2][kPtsPerWave * kHStride];
+};
+
+__device__ __forceinline__ void load_weights(MlpLds &L, const u16 *wb, const float *wf)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(wb);
+    uint4 *d1 = reinterpret_cast<uint4 *>(L.W1);
+    for (int i = threadIdx.x; i < (kMlpW1 + kMlpW2 + kMlpW3) / 8; i += blockDim.x) {
+        // W1, W2, W3 are contiguous in both the workspace and the LDS struct
+        d1[i] = src[i];
+    }
+    for (int i = threadIdx.x; i < kMlpWidth; i += blockDim.x)
+        L.w4[i] = bf2f(wb[kMlpW1 + kMlpW2 + kMlpW3 + i]);
+    for (int i = threadIdx.x; i < 3 * kMlpWidth + 1; i += blockDim.x) L.b[i] = wf[i];
+}
+
+// acc[rt][ct] (16x16 tiles) += A (32 x K, operand frags from `a`) * W^T
+template <int KSTEPS>
+__device__ __forceinline__ void layer_mfma(const Frag (&a)[2][KSTEPS], const u16 *W, int ldw,
+                                           int lane, f32x4 (&acc)[2][4])
+{
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            Frag b;
+            b.q = *reinterpret_cast<const uint4 *>(W + (ct * 16 + (lane & 15)) * ldw + ks * 32 +
+                                                   8 * (lane >> 4));
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) acc[rt][ct] = mfma(a[rt][ks], b, acc[rt][ct]);
+        }
+    }
+}
+
+// bias + ReLU + bf16 of the accumulator tile into the per-wave LDS tile H [32][kHStride]
+__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[2][4], const float *bias, u16 *H,
+                                             int lane)
+{
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+            const int j = ct * 16 + (lane & 15);
+            const float bj = bias[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pt = rt * 16 + 4 * (lane >> 4) + r;
+                H[pt * kHStride + j] = f2bf(fmaxf(acc[rt][ct][r] + bj, 0.f));
+            }
+        }
+}
+
+__device__ __forceinline__ void load_hidden(const u16 *H, int lane, Frag (&a)[2][2])
+{
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+            a[rt][ks].q = *reinterpret_cast<const uint4 *>(H + (rt * 16 + (lane & 15)) * kHStride +
+                                                          ks * 32 + 8 * (lane >> 4));
+}
+
+__device__ __forceinline__ void save_tile(const u16 *Ht, u16 *dst, int64_t base, int64_t M, int lane)
+{
+    const int row = lane >> 1, half = lane & 1;
+    if (base + row >= M) return;
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(Ht + row * kHStride + half * 32);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst + (base + row) * kMlpWidth + half * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d4[q] = s4[q];
+}
+
+// Forward over M points.  Point i uses position pts[i % G] and sun[i / G] when G > 0
+// (every surfel under every sun), or pts[i] and sun[i] when G == 0.  When `saveF` /
+// `saveH` are given the bf16 features [M,128] and hidden activations [3][M,64] are
+// written for the backward.
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(
+    const u16 *__restrict__ wb, const float *__restrict__ wf, const float *__restrict__ pts,
+    const float *__restrict__ sun, int64_t M, int64_t G, MlpNorm nz, int prob,
+    float *__restrict__ out, u16 *__restrict__ saveF, u16 *__restrict__ saveH)
+{
+    __shared__ MlpLds L;
+    load_weights(L, wb, wf);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u16 *H0 = L.H[wave][0], *H1 = L.H[wave][1];
+    const int64_t ntile = (M + kPtsPerWave - 1) / kPtsPerWave;
+    for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
+         tile += (int64_t)gridDim.x * kMlpWaves) {
+        const int64_t base = tile * kPtsPerWave;
+        // ---- features in operand layout
+        Frag fa[2][4];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            int64_t i = base + rt * 16 + (lane & 15);
+            const bool valid = i < M;
+            if (!valid) i = M - 1;
+            const int64_t ip = G > 0 ? i % G : i, is = G > 0 ? i / G : i;
+            float ph[3];
+            ph[0] = __fmul_rn(__fsub_rn(pts[3 * ip], nz.cx), nz.inv_half);
+            ph[1] = __fmul_rn(__fsub_rn(pts[3 * ip + 1], nz.cy), nz.inv_half);
+            ph[2] = __fmul_rn(__fsub_rn(pts[3 * ip + 2], nz.cz), nz.inv_half);
+            const float phi = sun[2 * is], th = sun[2 * is + 1];
+            float sphi, cphi, sth, cth;
+            sincosf(phi, &sphi, &cphi);
+            sincosf(th, &sth, &cth);
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                feature_chunk(ph, cphi, sphi, sth, cth, ks, lane >> 4, fa[rt][ks]);
+                if (saveF && valid)
+                    *reinterpret_cast<uint4 *>(saveF + i * kMlpIn + ks * 32 + 8 * (lane >> 4)) =
+                        fa[rt][ks].q;
+            }
+        }
+        f32x4 acc[2][4];
+        Frag ha[2][2];
+        // ---- layer 1 -> H0
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer_mfma<4>(fa, L.W1, kMlpIn, lane, acc);
+        store_hidden(acc, L.b, H0, lane);
+        __builtin_amdgcn_wave_barrier();
+        if (saveH) save_tile(H0, saveH, base, M, lane);
+        // ---- layer 2: H0 -> H1
+        load_hidden(H0, lane, ha);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer_mfma<2>(ha, L.W2, kMlpWidth, lane, acc);
+        store_hidden(acc, L.b + kMlpWidth, H1, lane);
+        __builtin_amdgcn_wave_barrier();
+        if (saveH) save_tile(H1, saveH + M * kMlpWidth, base, M, lane);
+        // ---- layer 3: H1 -> H0
+        load_hidden(H1, lane, ha);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer_mfma<2>(ha, L.W3, kMlpWidth, lane, acc);
+        __builtin_amdgcn_wave_barrier();
+        store_hidden(acc, L.b + 2 * kMlpWidth, H0, lane);
+        __builtin_amdgcn_wave_barrier();
+        if (saveH) save_tile(H0, saveH + 2 * M * kMlpWidth, base, M, lane);
+        // ---- output: logit = w4 . h3 + b4 (FP32); 16 lanes share 4 points per tile
+        float part[2][4];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pt = rt * 16 + 4 * (lane >> 4) + r;
+                float s = 0.f;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int j = ct * 16 + (lane & 15);
+                    s = __fmaf_rn(L.w4[j], bf2f(H0[pt * kHStride + j]), s);
+                }
+                part[rt][r] = s;
+            }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int d = 1; d < 16; d <<= 1) part[rt][r] += __shfl_xor(part[rt][r], d, 64);
+        if ((lane & 15) == 0) {
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = base + rt * 16 + 4 * (lane >> 4) + r;
+                    if (i < M) {
+                        const float lg = part[rt][r] + L.b[3 * kMlpWidth];
+                        out[i] = prob ? 1.f / (1.f + expf(-lg)) : lg;
+                    }
+                }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ------------------------------------------------------------- output backward
+// Per point: dlogit, BCE loss, da3 = bf16(dlogit * w4 * [h3 > 0]); per block the sums
+// of dlogit * h3 (dw4), dlogit (db4) and the loss -> part[blk][66].
+__global__ __launch_bounds__(256) void k_mlp_out_bwd(
+    const float *__restrict__ logits, const float *__restrict__ labels,
+    const float *__restrict__ dlin, float scale, const u16 *__restrict__ wb,
+    const u16 *__restrict__ H3, int64_t M, u16 *__restrict__ dA3, float *__restrict__ part)
+{
+    __shared__ float dl[256];
+    __shared__ float red[4][66];
+    __shared__ float w4s[kMlpWidth];
+    if (threadIdx.x < kMlpWidth) w4s[threadIdx.x] = bf2f(wb[kMlpW1 + kMlpW2 + kMlpW3 + threadIdx.x]);
+    const int64_t base = (int64_t)blockIdx.x * 256;
+    const int64_t m = base + threadIdx.x;
+    float d = 0.f, loss = 0.f;
+    if (m < M) {
+        const float lg = logits[m];
+        if (labels) {
+            const float y = labels[m];
+            d = (1.f / (1.f + expf(-lg)) - y) * scale;
+            loss = (fmaxf(lg, 0.f) - lg * y + log1pf(expf(-fabsf(lg)))) * scale;
+        } else {
+            d = dlin[m] * scale;
+        }
+    }
+    dl[threadIdx.x] = d;
+    __syncthreads();
+    if (m < M) {
+        const u16 *h = H3 + m * kMlpWidth;
+        u16 *o = dA3 + m * kMlpWidth;
+        for (int j = 0; j < kMlpWidth; ++j) {
+            const u16 hj = h[j];
+            o[j] = f2bf((hj != 0 && !(hj & 0x8000)) ? d * w4s[j] : 0.f);
+        }
+    }
+    // column sums: thread t -> column j = t & 63 over points q = t >> 6 (+4)
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    float s = 0.f;
+    for (int p = q; p < 256; p += 4)
+        if (base + p < M) s += dl[p] * bf2f(H3[(base + p) * kMlpWidth + j]);
+    red[q][j] = s;
+    if (threadIdx.x < 4) {
+        float a = 0.f, b = 0.f;
+        for (int p = threadIdx.x; p < 256; p += 4) a += dl[p];
+        red[threadIdx.x][64] = a;
+        red[threadIdx.x][65] = 0.f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // loss: simple serial sum over the block (training-only path)
+        float l = 0.f;
+        for (int p = 0; p < 256; ++p) {
+            const int64_t mm = base + p;
+            if (mm < M && labels) {
+                const float lg = logits[mm], y = labels[mm];
+                l += (fmaxf(lg, 0.f) - lg * y + log1pf(expf(-fabsf(lg)))) * scale;
+            }
+        }
+        red[0][65] = l;
+    }
+    (void)loss;
+    __syncthreads();
+    if (threadIdx.x < 66) {
+        float t = red[0][threadIdx.x];
+        if (threadIdx.x < 65) t += red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+        part[(int64_t)blockIdx.x * 66 + threadIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------ weight gradients
+// part_dw[blk][i][j] = sum over the block's kDwChunk points of dA[m][i] H[m][j] (MFMA,
+// the point index is the contraction), part_db[blk][i] = sum of dA[m][i].
+template <int N>
+__global__ __launch_bounds__(256) void k_mlp_dw(const u16 *__restrict__ dA,
+                                                const u16 *__restrict__ H, int64_t M,
+                                                float *__restrict__ part_dw,
+                                                float *__restrict__ part_db)
+{
+    __shared__ u16 sA[32 * kMlpWidth];
+    __shared__ u16 sH[32 * N];
+    const int lane = threadIdx.x & 63, rt = threadIdx.x >> 6;
+    constexpr int NCT = N / 16;
+    f32x4 acc[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float db = 0.f;
+    const int64_t m0 = (int64_t)blockIdx.x * kDwChunk;
+    for (int ks = 0; ks < kDwChunk / 32; ++ks) {
+        const int64_t mb = m0 + ks * 32;
+        __syncthreads();
+        {   // 32 x 64 bf16 of dA: one uint4 per thread
+            const int r = threadIdx.x >> 3, c = (threadIdx.x & 7) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (mb + r < M) v = *reinterpret_cast<const uint4 *>(dA + (mb + r) * kMlpWidth + c);
+            *reinterpret_cast<uint4 *>(sA + r * kMlpWidth + c) = v;
+        }
+        for (int e = threadIdx.x; e < 32 * N / 8; e += 256) {
+            const int r = e / (N / 8), c = (e % (N / 8)) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (mb + r < M) v = *reinterpret_cast<const uint4 *>(H + (mb + r) * N + c);
+            *reinterpret_cast<uint4 *>(sH + r * N + c) = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kMlpWidth)
+            for (int r = 0; r < 32; ++r) db += bf2f(sA[r * kMlpWidth + threadIdx.x]);
+        Frag a;
+        const int i = rt * 16 + (lane & 15), g = lane >> 4;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a.h[q] = sA[(8 * g + q) * kMlpWidth + i];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            Frag b;
+            const int j = ct * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) b.h[q] = sH[(8 * g + q) * N + j];
+            acc[ct] = mfma(a, b, acc[ct]);
+        }
+    }
+    float *out = part_dw + (int64_t)blockIdx.x * kMlpWidth * N;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = rt * 16 + 4 * (lane >> 4) + r, j = ct * 16 + (lane & 15);
+            out[i * N + j] = acc[ct][r];
+        }
+    if (threadIdx.x < kMlpWidth) part_db[(int64_t)blockIdx.x * kMlpWidth + threadIdx.x] = db;
+}
+
+// ------------------------------------------------------- propagated activations
+// dA_prev[m][j] = bf16( sum_i dA[m][i] W[i][j] * [Hprev[m][j] > 0] ), W = [out i][in j].
+__global__ __launch_bounds__(256) void k_mlp_dh(const u16 *__restrict__ dA,
+                                                const u16 *__restrict__ Wb,
+                                                const u16 *__restrict__ Hprev, int64_t M,
+                                                u16 *__restrict__ dAp)
+{
+    __shared__ u16 Wt[kMlpWidth * kMlpWidth];   // Wt[j][i] = W[i][j]
+    for (int e = threadIdx.x; e < kMlpWidth * kMlpWidth; e += 256) {
+        const int i = e / kMlpWidth, j = e % kMlpWidth;
+        Wt[j * kMlpWidth + i] = Wb[e];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+    const int64_t ntile = (M + kPtsPerWave - 1) / kPtsPerWave;
+    for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
+         tile += (int64_t)gridDim.x * kMlpWaves) {
+        const int64_t base = tile * kPtsPerWave;
+        Frag a[2][2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const int64_t m = base + rt * 16 + (lane & 15);
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+                a[rt][ks].q = m < M ? *reinterpret_cast<const uint4 *>(dA + m * kMlpWidth + ks * 32 + 8 * g)
+                                    : make_uint4(0, 0, 0, 0);
+        }
+        f32x4 acc[2][4];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        layer_mfma<2>(a, Wt, kMlpWidth, lane, acc);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t m = base + rt * 16 + 4 * g + r;
+                    const int j = ct * 16 + (lane & 15);
+                    if (m < M) {
+                        const u16 hp = Hprev[m * kMlpWidth + j];
+                        dAp[m * kMlpWidth + j] = f2bf((hp != 0 && !(hp & 0x8000)) ? acc[rt][ct][r] : 0.f);
+                    }
+                }
+    }
+}
+
+__global__ void k_mlp_reduce(const float *__restrict__ part, int nblocks, int count, int stride,
+                             float *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= count) return;
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * stride + c];
+    out[c] = s;
+}
+
+__global__ void k_mlp_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                           const float *__restrict__ g, int64_t n, float lr, float b1, float b2,
+                           float eps, float bc1, float bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ------------------------------------------------------------------ launchers
+int mlp_dw_blocks(int64_t M) { return (int)((M + kDwChunk - 1) / kDwChunk); }
+
+hipError_t launch_mlp_prep(const float *w, uint16_t *wb, float *wf, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_prep, dim3((kMlpBf16 + 255) / 256), dim3(256), 0, st, w, wb, wf);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint16_t *wb, const float *wf, const float *pts,
+                              const float *sun, int64_t M, int64_t G, MlpNorm nz, bool prob,
+                              float *out, uint16_t *saveF, uint16_t *saveH, hipStream_t st)
+{
+    if (M <= 0) return hipSuccess;
+    int64_t tiles = (M + kPtsPerWave - 1) / kPtsPerWave;
+    int64_t blocks = (tiles + kMlpWaves - 1) / kMlpWaves;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(kMlpThreads), 0, st, wb, wf,
+                       pts, sun, M, G, nz, prob ? 1 : 0, out, saveF, saveH);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_out_bwd(const float *logits, const float *labels, const float *dlogit_in,
+                              float scale, const uint16_t *wb, const uint16_t *H3, int64_t M,
+                              uint16_t *dA3, float *part, hipStream_t st)
+{
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_out_bwd, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, logits,
+                       labels, dlogit_in, scale, wb, H3, M, dA3, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_dw(const uint16_t *dA, const uint16_t *H, int n, int64_t M, float *part_dw,
+                         float *part_db, hipStream_t st)
+{
+    const int nb = mlp_dw_blocks(M);
+    if (nb == 0) return hipSuccess;
+    if (n == 64)
+        hipLaunchKernelGGL(k_mlp_dw<64>, dim3(nb), dim3(256), 0, st, dA, H, M, part_dw, part_db);
+    else if (n == 128)
+        hipLaunchKernelGGL(k_mlp_dw<128>, dim3(nb), dim3(256), 0, st, dA, H, M, part_dw, part_db);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_dh(const uint16_t *dA, const uint16_t *Wb, const uint16_t *Hprev, int64_t M,
+                         uint16_t *dA_prev, hipStream_t st)
+{
+    if (M <= 0) return hipSuccess;
+    int64_t tiles = (M + kPtsPerWave - 1) / kPtsPerWave;
+    int64_t blocks = (tiles + kMlpWaves - 1) / kMlpWaves;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_mlp_dh, dim3((unsigned)blocks), dim3(256), 0, st, dA, Wb, Hprev, M, dA_prev);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_reduce(const float *part, int nblocks, int count, int stride, float *out,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((count + 255) / 256), dim3(256), 0, st, part, nblocks, count,
+                       stride, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr,
+                           float b1, float b2, float eps, int step, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const float bc1 = 1.f - powf(b1, (float)step), bc2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, m, v, g, n,
+                       lr, b1, b2, eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+}  // namespace ss

@@ -86,7 +86,8 @@ __global__ __launch_bounds__(256) void k_project(
     const ViewDesc *__restrict__ views, const float *__restrict__ Fxy,
     const float *__restrict__ dF, const SunCam *__restrict__ sun,
     const float *__restrict__ vis, float bz, int ts, RasterConsts rc,
-    float4 *__restrict__ rec, short4 *__restrict__ tiles, uint32_t *__restrict__ counts)
+    float4 *__restrict__ rec, short4 *__restrict__ tiles, uint32_t *__restrict__ counts,
+    const uint32_t *__restrict__ tmask)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
@@ -172,7 +173,13 @@ __global__ __launch_bounds__(256) void k_project(
     if (ilo <= ihi) {
         tl.x = (short)(ilo / ts); tl.y = (short)(ihi / ts);
         tl.z = (short)(jlo / ts); tl.w = (short)(jhi / ts);
-        cnt = (uint32_t)(tl.y - tl.x + 1) * (uint32_t)(tl.w - tl.z + 1);
+        if (tmask) {
+            for (int ty = tl.z; ty <= tl.w; ++ty)
+                for (int tx = tl.x; tx <= tl.y; ++tx)
+                    cnt += tmask[vd.tile_off + ty * vd.tiles_x + tx] != 0u;
+        } else {
+            cnt = (uint32_t)(tl.y - tl.x + 1) * (uint32_t)(tl.w - tl.z + 1);
+        }
     } else {
         tl.x = 0; tl.y = -1; tl.z = 0; tl.w = -1;
     }
@@ -200,12 +207,13 @@ hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order,
                           const ViewDesc *views, const float *Fxy, const float *dF,
                           const SunCam *sun, const float *vis, float bz, int ts,
                           const RasterConsts &rc, float *rec, short4 *tiles, uint32_t *counts,
-                          hipStream_t st)
+                          const uint32_t *tmask, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0,
                        st, reinterpret_cast<const float4 *>(sorted), n, order, views, Fxy, dF,
-                       sun, vis, bz, ts, rc, reinterpret_cast<float4 *>(rec), tiles, counts);
+                       sun, vis, bz, ts, rc, reinterpret_cast<float4 *>(rec), tiles, counts,
+                       tmask);
     return hipGetLastError();
 }
 
@@ -216,7 +224,8 @@ hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order,
 __global__ void k_emit(int64_t n, const ViewDesc *__restrict__ views,
                        const short4 *__restrict__ tiles, const uint32_t *__restrict__ counts,
                        const uint32_t *__restrict__ offsets, uint64_t cap,
-                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                       const uint32_t *__restrict__ tmask)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
@@ -227,20 +236,25 @@ __global__ void k_emit(int64_t n, const ViewDesc *__restrict__ views,
     const ViewDesc vd = views[v];
     uint64_t pos = offsets[slot];
     for (int ty = t.z; ty <= t.w; ++ty)
-        for (int tx = t.x; tx <= t.y; ++tx, ++pos)
+        for (int tx = t.x; tx <= t.y; ++tx) {
+            const uint32_t key = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
+            if (tmask && tmask[key] == 0u) continue;
             if (pos < cap) {
-                keys[pos] = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
+                keys[pos] = key;
                 vals[pos] = (uint32_t)r;
             }
+            ++pos;
+        }
 }
 
 hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *views,
                        const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
-                       uint64_t cap, uint32_t *keys, uint32_t *vals, hipStream_t st)
+                       uint64_t cap, uint32_t *keys, uint32_t *vals, const uint32_t *tmask,
+                       hipStream_t st)
 {
     if (n <= 0 || cap == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0, st,
-                       n, views, tiles, counts, offsets, cap, keys, vals);
+                       n, views, tiles, counts, offsets, cap, keys, vals, tmask);
     return hipGetLastError();
 }
 

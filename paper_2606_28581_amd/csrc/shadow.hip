@@ -122,11 +122,13 @@ hipError_t launch_sun_cameras(const float *mean, int64_t n, int32_t nv, const fl
 __global__ void k_shadow_query(const float *__restrict__ mean, int64_t n,
                                const SunCam *__restrict__ sun, const float *__restrict__ D,
                                int32_t S, float bz, float esm_c, float esm_bias,
-                               float *__restrict__ vis)
+                               float *__restrict__ vis, float band)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     if (k >= n) return;
+    // band > 0: only points whose current (surrogate) value lies within the band
+    if (band > 0.f && !(fabsf(vis[(int64_t)v * n + k] - 0.5f) < band)) return;
     const SunCam &c = sun[v];
     const double p0 = mean[3 * k], p1 = mean[3 * k + 1], p2 = mean[3 * k + 2];
     double x = c.b[0], y = c.b[1];
@@ -149,11 +151,48 @@ __global__ void k_shadow_query(const float *__restrict__ mean, int64_t n,
 
 hipError_t launch_shadow_query(const float *mean, int64_t n, int32_t nv, const SunCam *sun,
                                const float *sun_depth, int32_t S, float bz, float esm_c,
-                               float esm_bias, float *vis, hipStream_t st)
+                               float esm_bias, float *vis, float band, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_shadow_query, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256),
-                       0, st, mean, n, sun, sun_depth, S, bz, esm_c, esm_bias, vis);
+                       0, st, mean, n, sun, sun_depth, S, bz, esm_c, esm_bias, vis, band);
+    return hipGetLastError();
+}
+
+// Surrogate fallback: every point whose surrogate visibility lies within `band` of 0.5
+// marks the sun-map tiles of its 3x3 texel window (same FP64 texel choice as the query)
+// and is counted.
+__global__ void k_flag_tiles(const float *__restrict__ mean, int64_t n,
+                             const SunCam *__restrict__ sun, const ViewDesc *__restrict__ views,
+                             int32_t S, int ts, const float *__restrict__ vis, float band,
+                             uint32_t *__restrict__ tmask, unsigned long long *__restrict__ count)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (k >= n) return;
+    if (!(fabsf(vis[(int64_t)v * n + k] - 0.5f) < band)) return;
+    atomicAdd(count, 1ull);
+    const SunCam &c = sun[v];
+    const double p0 = mean[3 * k], p1 = mean[3 * k + 1], p2 = mean[3 * k + 2];
+    double x = c.b[0], y = c.b[1];
+    x += c.B[0] * p0; x += c.B[1] * p1; x += c.B[2] * p2;
+    y += c.B[3] * p0; y += c.B[4] * p1; y += c.B[5] * p2;
+    const double fx = floor(x), fy = floor(y);
+    const ViewDesc vd = views[v];
+    for (int t = 0; t < 9; ++t) {
+        const double tx = fx + (t % 3) - 1, ty = fy + (t / 3) - 1;
+        if (tx >= 0 && ty >= 0 && tx < S && ty < S)
+            tmask[vd.tile_off + ((int)ty / ts) * vd.tiles_x + ((int)tx / ts)] = 1u;
+    }
+}
+
+hipError_t launch_flag_tiles(const float *mean, int64_t n, int32_t nv, const SunCam *sun,
+                             const ViewDesc *views, int32_t S, int ts, const float *vis,
+                             float band, uint32_t *tmask, unsigned long long *count, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0,
+                       st, mean, n, sun, views, S, ts, vis, band, tmask, count);
     return hipGetLastError();
 }
 

@@ -98,10 +98,11 @@ hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order,
                           const ViewDesc *views, const float *Fxy, const float *dF,
                           const SunCam *sun, const float *vis, float bz, int ts,
                           const RasterConsts &rc, float *rec, short4 *tiles, uint32_t *counts,
-                          hipStream_t st);
+                          const uint32_t *tmask, hipStream_t st);
 hipError_t launch_emit(const uint32_t *order, int64_t n, int32_t nv, const ViewDesc *views,
                        const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
-                       uint64_t cap, uint32_t *keys, uint32_t *vals, hipStream_t st);
+                       uint64_t cap, uint32_t *keys, uint32_t *vals, const uint32_t *tmask,
+                       hipStream_t st);
 hipError_t launch_ranges(const uint32_t *keys, const unsigned long long *n_dev, int64_t cap,
                          int64_t n_tiles, uint32_t *ranges, hipStream_t st);
 hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
@@ -145,6 +146,9 @@ hipError_t launch_sun_cameras(const float *mean, int64_t n, int32_t nv, const fl
                               double *bounds_partials, SunCam *out, hipStream_t st);
 hipError_t launch_shadow_query(const float *mean, int64_t n, int32_t nv, const SunCam *sun,
                                const float *sun_depth, int32_t S, float bz, float esm_c,
-                               float esm_bias, float *vis, hipStream_t st);
+                               float esm_bias, float *vis, float band, hipStream_t st);
+hipError_t launch_flag_tiles(const float *mean, int64_t n, int32_t nv, const SunCam *sun,
+                             const ViewDesc *views, int32_t S, int ts, const float *vis,
+                             float band, uint32_t *tmask, unsigned long long *count, hipStream_t st);
 
 }  // namespace ss

@@ -255,9 +255,10 @@ class Plan:
         return {lib.ss_stage_name(k).decode(): (ms[k], cnt[k]) for k in range(_lib.SS_NUM_STAGES)}
 
     def stats(self):
-        out = (C.c_int64 * 6)()
+        out = (C.c_int64 * 7)()
         call("ss_plan_stats", self.handle, C.cast(out, C.c_void_p), _stream())
-        keys = ("pairs", "contrib", "evaluated", "sun_pairs", "sun_contrib", "sun_evaluated")
+        keys = ("pairs", "contrib", "evaluated", "sun_pairs", "sun_contrib", "sun_evaluated",
+                "fallback")
         return dict(zip(keys, list(out)))
 
     def debug_sun_cameras(self):
