@@ -91,11 +91,13 @@ __global__ void k_scan_reduce(const uint32_t *in, int64_t len, uint32_t *partial
 }
 
 // One block: exclusive scan of the per-chunk sums in 64-bit, overflow detection.
-__global__ void k_scan_partials(uint32_t *partials, int64_t nparts, uint32_t *out_total,
-                                unsigned long long *counters, int which, uint32_t *flags,
-                                uint64_t cap)
+constexpr int kScanPartialsThreads = 1024;
+
+__global__ __launch_bounds__(kScanPartialsThreads) void k_scan_partials(
+    uint32_t *partials, int64_t nparts, uint32_t *out_total, unsigned long long *counters,
+    int which, uint32_t *flags, uint64_t cap)
 {
-    __shared__ unsigned long long lds[kSortWaves];
+    __shared__ unsigned long long lds[kScanPartialsThreads / kWave];
     __shared__ unsigned long long carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -164,8 +166,8 @@ hipError_t scan_pair_counts(const uint32_t *counts, int64_t n, int32_t nv,
     if (nb > 0)
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kSortThreads), 0, st,
                            counts, len, partials);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, st, partials, nb, out + len,
-                       counters, which, flags, cap);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanPartialsThreads), 0, st, partials, nb,
+                       out + len, counters, which, flags, cap);
     if (nb > 0)
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kSortThreads), 0, st, counts,
                            len, partials, out);
@@ -210,9 +212,10 @@ __global__ void k_hist_scan_reduce(uint32_t *hist, int64_t len, uint32_t *partia
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
-__global__ void k_hist_scan_partials(uint32_t *partials, int64_t nparts)
+__global__ __launch_bounds__(kScanPartialsThreads) void k_hist_scan_partials(uint32_t *partials,
+                                                                             int64_t nparts)
 {
-    __shared__ uint32_t lds[kSortWaves * 4];
+    __shared__ uint32_t lds[kScanPartialsThreads / kWave];
     __shared__ uint32_t carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -329,7 +332,8 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
                            n_dev, cap, n_host, shift, hist, (int)nb);
         hipLaunchKernelGGL(k_hist_scan_reduce, dim3((unsigned)nparts), dim3(kSortThreads), 0,
                            st, hist, hlen, parts);
-        hipLaunchKernelGGL(k_hist_scan_partials, dim3(1), dim3(1024), 0, st, parts, nparts);
+        hipLaunchKernelGGL(k_hist_scan_partials, dim3(1), dim3(kScanPartialsThreads), 0, st, parts,
+                           nparts);
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nparts), dim3(kSortThreads), 0, st,
                            hist, hlen, parts, hist);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,

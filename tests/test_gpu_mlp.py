@@ -94,8 +94,9 @@ def test_adam_matches_oracle():
     g = rng.normal(size=n).astype(np.float32)
     tw, tm, tv = cuda(w), cuda(m), cuda(v)
     sg.adam(tw, tm, tv, cuda(g), lr=1e-3, step=3)
+    f = lambda x: float(np.float32(x))    # the kernel receives FP32 hyper-parameters
     rw, rm, rv = om.adam(w.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
-                         g.astype(np.float64), 1e-3, 3)
+                         g.astype(np.float64), f(1e-3), 3, beta1=f(0.9), beta2=f(0.999), eps=f(1e-8))
     np.testing.assert_allclose(to_np(tm), rm, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(to_np(tv), rv, rtol=1e-5, atol=1e-9)
     np.testing.assert_allclose(to_np(tw), rw, rtol=1e-5, atol=1e-6)

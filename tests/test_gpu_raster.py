@@ -211,3 +211,31 @@ def test_forward_deterministic_backward_nearly():
     g2 = plan.backward(surf, views, out, dI, dD, dN)
     for k in GRAD_KEYS:
         assert rel_err(to_np(g2[k]), g1[k]) < 1e-5, k
+
+
+def test_pair_count_scan_beyond_one_pass_of_the_partials_kernel():
+    """More than 1024 x 4096 (view, surfel) slots: the pair-count scan's chunk totals
+    take several passes of its single-block kernel (regression: the per-wave LDS array
+    was sized for 4 of its 16 waves, so the carry broke after the first pass)."""
+    views = tuple((24 + (v % 5), 20 + (v % 7)) for v in range(40))
+    sc = synth.make_scene(synth.tiny(n_surfels=110_000, views=views, seed=41, colour=False,
+                                     suns=False))
+    assert 110_000 * 40 > 1024 * 4096
+    plan, surf, views_t = make_plan(sc)
+    K, _ = plan.count_pairs(surf, views_t)
+    st = oracle_settings()
+    expect = 0
+    per_view = []
+    for v, (W, H) in enumerate(zip(sc["width"], sc["height"])):
+        B, bb = oracle.view_camera(sc, v)
+        _, _, _, tiles = oracle.binning(sc, B, bb, int(W), int(H), 16, st)
+        cnt = np.where(tiles[:, 0] <= tiles[:, 1],
+                       (tiles[:, 1] - tiles[:, 0] + 1) * (tiles[:, 3] - tiles[:, 2] + 1), 0)
+        per_view.append(tiles)
+        expect += int(cnt.sum())
+    assert K == expect
+    plan.forward(surf, views_t)
+    b = plan.debug_binning(0)
+    for v in (0, 17, 39):
+        np.testing.assert_array_equal(b["tiles"][v], per_view[v])
+    assert b["lists"].shape[0] == expect
