@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="eager steps instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this many MiB (5 times) and exit; "
+                         "used to calibrate the profiler's FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
@@ -106,6 +109,15 @@ def main():
     import paper_2606_28581_amd as ss
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 5}))
+        return
     t0 = time.time()
     spec = synth.config(args.config)
     scene = synth.make_scene(spec)
