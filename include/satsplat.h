@@ -59,7 +59,8 @@ typedef struct ihipStream_t *ss_stream;   /* hipStream_t; NULL = default stream 
 typedef struct ss_raster_settings {
     uint32_t struct_size;   /* sizeof(ss_raster_settings)                              */
     int32_t  tile_size;     /* 8, 16 (paper default, Sec. 3.2) or 32                    */
-    int32_t  batch_depth;   /* surfel records staged in LDS per batch: 32,64,128,256    */
+    int32_t  batch_depth;   /* surfel records staged in LDS per batch (1..256; capped at
+                               tile_size^2, one record per thread)                      */
     float    alpha_min;     /* skip a surfel at a pixel when alpha < alpha_min (1/255)  */
     float    alpha_max;     /* alpha = min(alpha_max, o * G) (0.99)                     */
     float    T_min;         /* stop before transmittance would drop below T_min (1e-4) */
@@ -247,8 +248,9 @@ ss_status ss_graph_destroy(ss_graph *graph);
  * tile_size in {8, 16, 32} x batch_depth in {32, 64, 128, 256} and leaves the plan on
  * the fastest; *best receives those settings, best_ms its step time.  Candidates whose
  * pairs exceed the bound capacities are skipped (bind capacities counted with
- * tile_size 8, the largest pair count, to try all).  table (host, may be NULL) receives
- * 12 x 3 doubles: tile, batch, ms (ms < 0: skipped). */
+ * tile_size 8, the largest pair count, to try all); so are batch depths above the tile's
+ * thread count (tile_size^2: one staged record per thread).  table (host, may be NULL)
+ * receives 12 x 3 doubles: tile, batch, ms (ms < 0: skipped). */
 ss_status ss_autotune(ss_plan *plan, const ss_surfels *s, const ss_views *v,
                       const ss_step_io *io, int32_t reps, ss_raster_settings *best,
                       double *best_ms, double *table, ss_stream stream);

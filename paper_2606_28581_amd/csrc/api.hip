@@ -848,6 +848,14 @@ ss_status ss_autotune(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
             c.tile_size = tiles[ti];
             c.batch_depth = batches[bi];
             double ms = -1.0;
+            if (c.batch_depth > c.tile_size * c.tile_size) {   // one staged record per thread
+                if (table) {
+                    table[3 * row] = c.tile_size;
+                    table[3 * row + 1] = c.batch_depth;
+                    table[3 * row + 2] = ms;
+                }
+                continue;
+            }
             if ((e = ss_plan_set_settings(p, &c)) != SS_OK) break;
             int64_t km = 0, ks = 0;
             if ((e = ss_count_pairs(p, s, v, &km, &ks, stream)) != SS_OK) break;

@@ -352,24 +352,43 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     float Tr = 1.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, aV = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
     int lastpos = 0, ncontrib = 0, neval = 0;
     bool done = !inside;
-    const int batch = rc.batch;
+    // batch <= NT: one record per thread.  The next batch is fetched into registers
+    // (NV4 independent float4 loads per thread) while the current one is composited.
+    const int batch = min(rc.batch, NT);
+    float4 q[NV4];
+    auto fetch = [&](uint32_t base, int cnt) {
+        if (tid < cnt) {
+            const uint32_t idx = min(lists[base + tid], (uint32_t)(n - 1));
+            const float4 *src = recv + (size_t)idx * kRecVec4;
+#pragma unroll
+            for (int k = 0; k < NV4; ++k) q[k] = src[k];
+        }
+    };
+    if (start < end) fetch(start, (int)min((uint32_t)batch, end - start));
     for (uint32_t b0 = start; b0 < end; b0 += batch) {
         const int nb = (int)min((uint32_t)batch, end - b0);
         __syncthreads();
-        for (int e = tid; e < nb * NV4; e += NT) {
-            const int rr = e / NV4, q = e - rr * NV4;
-            const uint32_t idx = min(lists[b0 + rr], (uint32_t)(n - 1));
-            lds[rr * kRecVec4 + q] = recv[(size_t)idx * kRecVec4 + q];
+        if (tid < nb) {
+#pragma unroll
+            for (int k = 0; k < NV4; ++k) lds[tid * kRecVec4 + k] = q[k];
         }
         __syncthreads();
+        const uint32_t b1 = b0 + batch;
+        if (b1 < end) fetch(b1, (int)min((uint32_t)batch, end - b1));
         if (__ballot(!done) != 0) {
+            float4 c0 = lds[0], c1 = lds[1], c2 = lds[2], c3 = lds[3];
             for (int j = 0; j < nb; ++j) {
-                const float4 *R = lds + j * kRecVec4;
-                const float4 r0 = R[0];
-                if (!box_hits(r0.x, r0.y, wx0, wy0)) continue;
+                const float4 r0 = c0, r1 = c1, r2 = c2, r3 = c3;
+                if (j + 1 < nb) {   // next record's fields load while this one is evaluated
+                    const float4 *Rn = lds + (j + 1) * kRecVec4;
+                    c0 = Rn[0]; c1 = Rn[1]; c2 = Rn[2]; c3 = Rn[3];
+                }
+                // 8x8 tiles: the binning already guarantees the record overlaps the wave's
+                // pixels; larger tiles cull per 8x8 wave sub-block
+                if (TS > 8 && !box_hits(r0.x, r0.y, wx0, wy0)) continue;
+                if (__ballot(!done) == 0) break;
                 if (done) continue;
                 ++neval;
-                const float4 r1 = R[1], r2 = R[2], r3 = R[3];
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 if (e.alpha >= rc.alpha_min) {
                     const float Tn = __fmul_rn(Tr, __fsub_rn(1.f, e.alpha));
@@ -380,6 +399,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                         const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
                         aD = __fmaf_rn(w, z, aD);
                         if (!DEPTH_ONLY) {
+                            const float4 *R = lds + j * kRecVec4;
                             const float4 r4 = R[4], r5 = R[5];
                             a0 = __fmaf_rn(w, r4.x, a0);
                             a1 = __fmaf_rn(w, r4.y, a1);
@@ -461,7 +481,7 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
-    const size_t lds = (size_t)rc.batch * kRecVec4 * sizeof(float4);
+    const size_t lds = (size_t)min(rc.batch, ts * ts) * kRecVec4 * sizeof(float4);
 #define SS_FWD(TS_)                                                                              \
     if (ts == TS_) {                                                                             \
         if (depth_only)                                                                          \
@@ -480,47 +500,57 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
 }
 
 // ------------------------------------------------------- wave transpose reduction
-// 16 per-lane values -> lane l (l % 4 == 0) holds the wave sum of value l / 4.
-// 5 exchange rounds move halves of the remaining vector (8+4+2+1+1+1 shuffles).
+// 16 per-lane values -> lane l holds the wave sum of value (l >> 2) & 15 (lanes with
+// l % 4 == 0 then hold all 16 sums).  Each level halves the vector a lane carries: the
+// two cross-row levels use gfx950's lane swaps (permlane32 / permlane16: one VALU op
+// exchanges half of two registers between the partner rows, then one add), the two
+// in-row levels use DPP row mirrors, the last two are full DPP quad sums.  No LDS.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __builtin_amdgcn_update_dpp(0.f, v, CTRL, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ void swap_rows32(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void swap_rows16(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
 __device__ __forceinline__ float wave_transpose_reduce16(float (&x)[16], int lane)
 {
     float y8[8], y4[4], y2[2];
-    {
-        const bool up = lane & 32;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float send = up ? x[k] : x[k + 8];
-            const float keep = up ? x[k + 8] : x[k];
-            y8[k] = keep + __shfl_xor(send, 32, 64);
-        }
+    for (int k = 0; k < 8; ++k) {           // lanes 0-31 keep value k, 32-63 value k + 8
+        float a = x[k], b = x[k + 8];
+        swap_rows32(a, b);
+        y8[k] = a + b;
     }
-    {
-        const bool up = lane & 16;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float send = up ? y8[k] : y8[k + 4];
-            const float keep = up ? y8[k + 4] : y8[k];
-            y4[k] = keep + __shfl_xor(send, 16, 64);
-        }
+    for (int k = 0; k < 4; ++k) {           // even rows keep k, odd rows k + 4
+        float a = y8[k], b = y8[k + 4];
+        swap_rows16(a, b);
+        y4[k] = a + b;
     }
-    {
-        const bool up = lane & 8;
+    const bool b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const float send = up ? y4[k] : y4[k + 2];
-            const float keep = up ? y4[k + 2] : y4[k];
-            y2[k] = keep + __shfl_xor(send, 8, 64);
-        }
+    for (int k = 0; k < 2; ++k) {           // row mirror: partner 15 - i differs in bit 3
+        const float keep = b3 ? y4[k + 2] : y4[k];
+        const float send = b3 ? y4[k] : y4[k + 2];
+        y2[k] = keep + dpp<0x140>(send);
     }
-    float y;
-    {
-        const bool up = lane & 4;
-        const float send = up ? y2[0] : y2[1];
-        const float keep = up ? y2[1] : y2[0];
-        y = keep + __shfl_xor(send, 4, 64);
-    }
-    y += __shfl_xor(y, 2, 64);
-    y += __shfl_xor(y, 1, 64);
+    // half-row mirror: partner 7 - i differs in bit 2
+    float y = (b2 ? y2[1] : y2[0]) + dpp<0x141>(b2 ? y2[0] : y2[1]);
+    y += dpp<0x4E>(y);                      // quad_perm [2,3,0,1]
+    y += dpp<0xB1>(y);                      // quad_perm [1,0,3,2]
     return y;
 }
 
@@ -548,7 +578,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
     constexpr int NT = TS * TS;
     constexpr int NW = NT / 64;
     extern __shared__ float4 lds[];
-    uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + rc.batch * kRecVec4);
+    uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + min(rc.batch, NT) * kRecVec4);
     __shared__ float red[NW][16];
     __shared__ int max_last;
     const int tile = blockIdx.x;
@@ -624,43 +654,67 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
     const float4 *recv = rec + (size_t)v * (size_t)n * kRecVec4;
     float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
     float gS = 0.f;
-    const int batch = rc.batch;
+    const int batch = min(rc.batch, NT);
     const float two_is2 = 2.f * rc.inv_s2;
     const int blk_last = min(max_last, tile_len);   // a stale `last` cannot read past the list
+    // one record per thread; the batch before the current one (back to front) is
+    // fetched into registers while the current one is processed
+    float4 q[kRecVec4];
+    uint32_t qidx = 0;
+    auto fetch = [&](int bb, int cnt) {
+        if (tid < cnt) {
+            qidx = min(lists[start + bb + tid], (uint32_t)(n - 1));
+            const float4 *src = recv + (size_t)qidx * kRecVec4;
+#pragma unroll
+            for (int k = 0; k < kRecVec4; ++k) q[k] = src[k];
+        }
+    };
+    if (blk_last > 0) {
+        const int bb = blk_last > batch ? blk_last - batch : 0;
+        fetch(bb, blk_last - bb);
+    }
     for (int bend = blk_last; bend > 0; bend -= batch) {
         const int bb = bend > batch ? bend - batch : 0;
         const int nb = bend - bb;
         __syncthreads();
-        for (int e = tid; e < nb * kRecVec4; e += NT) {
-            const int rr = e / kRecVec4, q = e - rr * kRecVec4;
-            const uint32_t idx = min(lists[start + bb + rr], (uint32_t)(n - 1));
-            lds[rr * kRecVec4 + q] = recv[(size_t)idx * kRecVec4 + q];
+        if (tid < nb) {
+#pragma unroll
+            for (int k = 0; k < kRecVec4; ++k) lds[tid * kRecVec4 + k] = q[k];
+            lds_idx[tid] = qidx;
         }
-        for (int e = tid; e < nb; e += NT) lds_idx[e] = min(lists[start + bb + e], (uint32_t)(n - 1));
         __syncthreads();
+        if (bb > 0) {
+            const int pb = bb > batch ? bb - batch : 0;
+            fetch(pb, bb - pb);
+        }
+        float4 c0 = lds[(nb - 1) * kRecVec4], c1 = lds[(nb - 1) * kRecVec4 + 1];
+        float4 c2 = lds[(nb - 1) * kRecVec4 + 2], c3 = lds[(nb - 1) * kRecVec4 + 3];
         for (int j = nb - 1; j >= 0; --j) {
+            const float4 r0 = c0, r1 = c1, r2 = c2, r3 = c3;
+            if (j > 0) {   // previous record's fields load while this one is processed
+                const float4 *Rp = lds + (j - 1) * kRecVec4;
+                c0 = Rp[0]; c1 = Rp[1]; c2 = Rp[2]; c3 = Rp[3];
+            }
             const int pos = bb + j;
-            const float4 *R = lds + j * kRecVec4;
-            const float4 r0 = R[0];
-            if (!box_hits(r0.x, r0.y, wx0, wy0)) continue;
+            if (TS > 8 && !box_hits(r0.x, r0.y, wx0, wy0)) continue;
             float gr[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) gr[k] = 0.f;
             bool contrib = false;
             if (pos < mylast) {
-                const float4 r1 = R[1], r2 = R[2], r3 = R[3];
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 if (e.alpha >= rc.alpha_min) {
                     contrib = true;
+                    const float4 *R = lds + j * kRecVec4;
                     const float4 r4 = R[4], r5 = R[5];
-                    const float om = 1.f - e.alpha;
-                    const float Tb = Tr / om;
+                    const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
+                    const float Tb = Tr * rom;
                     const float w = e.alpha * Tb;
                     const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
                     float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
                                gN1 * r5.y + gN2 * r5.z;
                     if (HAS_VIS) gf += gV * r4.w;
-                    const float dal = Tb * gf - gS / om;
+                    const float dal = Tb * gf - gS * rom;
                     gS += w * gf;
                     Tr = Tb;
                     const float dz = w * gD;
@@ -692,9 +746,9 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
                 }
             }
             if (__ballot(contrib) == 0) continue;
-            const float s = wave_transpose_reduce16(gr, lane);
+            const float sum = wave_transpose_reduce16(gr, lane);
             if ((lane & 3) == 0)
-                atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane >> 2), s);
+                atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane >> 2), sum);
         }
     }
 }
@@ -724,7 +778,7 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
-    const size_t lds = (size_t)rc.batch * (kRecVec4 * sizeof(float4) + sizeof(uint32_t));
+    const size_t lds = (size_t)min(rc.batch, ts * ts) * (kRecVec4 * sizeof(float4) + sizeof(uint32_t));
 #define SS_BWD(TS_)                                                                          \
     if (ts == TS_) {                                                                         \
         if (has_vis)                                                                         \
