@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="eager steps instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip training / evaluating the learned shadow surrogate")
+    ap.add_argument("--surrogate-epochs", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB (5 times) and exit; "
                          "used to calibrate the profiler's FETCH_SIZE / WRITE_SIZE counters")
@@ -95,6 +98,34 @@ def cpu_baseline(scene, n_pix, seed=5):
                 sample=f"{n_pix} seeded pixels of view 0 ({W}x{H}), forward {t1 - t0:.1f} s + "
                        f"backward {t2 - t1:.1f} s, FP64 brute force over all {scene['surfels']['mean'].shape[0]} "
                        f"surfels per pixel, no shadow pass")
+
+
+def surrogate_eval(ctx, args):
+    """Learned shadow surrogate on the 1M-surfel city: 10M labels from 1000 suns by the
+    geometric pass, GPU training, then 200 held-out suns: agreement of the lit/shadow
+    decision with the geometric pass (fallback band |p - 0.5| < 0.1) and ms per view of
+    both passes."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2606_28581_amd as ss
+    from paper_2606_28581_amd import surrogate as sg
+    from paper_2606_28581_amd import surrogate_train as st
+    t0 = time.time()
+    spec = synth.config(2)
+    scene = synth.make_scene(spec)
+    surf, views = ss.scene_to_device(scene, with_sun=False)
+    half = spec.extent / 2
+    zc = float(np.mean(scene["surfels"]["mean"][:, 2]))
+    net = sg.Mlp(ctx, np.array([0.0, 0.0, zc], np.float32), np.float32(1.0 / half))
+    cfg = st.TrainConfig(epochs=args.surrogate_epochs)
+    lab = st.ShadowLab(ctx, surf, views.Fxy, views.b_z, cfg.chunk)
+    w, tr = st.train(lab, net, cfg, log=log)
+    ev = st.evaluate(lab, net, w, cfg, log=log)
+    out = dict(workload="c4_surrogate_1M_city", **ev, training=tr,
+               total_s=round(time.time() - t0, 1))
+    out["surrogate_faster"] = ev["surrogate_ms_per_view"] < ev["plain_ms_per_view"]
+    return out
 
 
 def main():
@@ -239,6 +270,12 @@ def main():
         "kernels": {k: round(v["avg_ms"], 4) for k, v in kern.items()},
         "autotune": tune,
     }
+    if not args.no_surrogate:
+        log("[bench] learned shadow surrogate (train + held-out evaluation)")
+        del bufs, graph
+        plan = None
+        torch.cuda.empty_cache()
+        result["shadow_surrogate"] = surrogate_eval(ctx, args)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")
         result["cpu_baseline"] = cpu_baseline(scene, args.cpu_pixels)

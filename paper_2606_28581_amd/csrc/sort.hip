@@ -248,6 +248,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int shift, int nblocks)
 {
     __shared__ uint32_t wcnt[kSortWaves][256];
+    __shared__ uint32_t dbase[256];          // block-local start of each digit's run
+    __shared__ uint32_t gshift[256];         // global start minus local start, per digit
+    __shared__ uint32_t lds_w[kSortWaves];
+    __shared__ uint32_t skey[kSortTile], sval[kSortTile];
     const int64_t n = live_count(n_dev, cap, n_host);
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     if (base >= n) return;   // uniform over the block
@@ -279,14 +283,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     __syncthreads();
     {
+        // per digit: prefix over the waves, then an exclusive scan over the digits gives
+        // each digit's run inside the block; the run goes to offs[digit, block] globally
         const int d = threadIdx.x;
-        uint32_t run = offs[(int64_t)d * nblocks + blockIdx.x];
+        uint32_t run = 0;
 #pragma unroll
         for (int k = 0; k < kSortWaves; ++k) {
-            uint32_t c = wcnt[k][d];
+            const uint32_t c = wcnt[k][d];
             wcnt[k][d] = run;
             run += c;
         }
+        uint32_t tot;
+        const uint32_t excl = block_exclusive_scan(run, lds_w, &tot);
+        dbase[d] = excl;
+        gshift[d] = offs[(int64_t)d * nblocks + blockIdx.x] - excl;
     }
     __syncthreads();
 #pragma unroll
@@ -294,11 +304,23 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const int64_t i = wbase + it * kWave + lane;
         if (i < n) {
             const uint32_t d = (key[it] >> shift) & 255u;
-            const uint32_t pos = wcnt[w][d] + rank[it];
-            if (pos < n) {   // always true when histogram and scatter agree
-                kout[pos] = key[it];
-                vout[pos] = val[it];
+            const uint32_t lp = dbase[d] + wcnt[w][d] + rank[it];
+            if (lp < (uint32_t)kSortTile) {   // always true when the counts agree
+                skey[lp] = key[it];
+                sval[lp] = val[it];
             }
+        }
+    }
+    __syncthreads();
+    // digit runs are contiguous in LDS and in the output: consecutive threads write
+    // consecutive addresses within a run
+    const int nloc = (int)min((int64_t)kSortTile, n - base);
+    for (int i = threadIdx.x; i < nloc; i += kSortThreads) {
+        const uint32_t k = skey[i];
+        const uint32_t pos = gshift[(k >> shift) & 255u] + (uint32_t)i;
+        if (pos < n) {   // always true when histogram and scatter agree
+            kout[pos] = k;
+            vout[pos] = sval[i];
         }
     }
 }
