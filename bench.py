@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=1024)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training / evaluating the learned shadow surrogate")
-    ap.add_argument("--surrogate-epochs", type=int, default=3)
+    ap.add_argument("--surrogate-epochs", type=int, default=30)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB (5 times) and exit; "
                          "used to calibrate the profiler's FETCH_SIZE / WRITE_SIZE counters")

@@ -292,7 +292,7 @@ struct PairEval {
 
 __device__ __forceinline__ PairEval eval_pair(const float4 r0, const float4 r1, const float4 r2,
                                               const float4 r3, float fx, float fy,
-                                              const RasterConsts &rc)
+                                              const RasterConsts rc)
 {
     PairEval e;
     e.dx = __fsub_rn(__fsub_rn(fx, r0.z), r1.x);
@@ -318,11 +318,61 @@ __device__ __forceinline__ bool box_hits(float bx, float by, int wx0, int wy0)
     return xlo <= wx0 + 7 && xhi >= wx0 && ylo <= wy0 + 7 && yhi >= wy0;
 }
 
+// Workgroups go round-robin to the 8 XCDs, each with its own L2.  Handing every XCD a
+// contiguous run of tiles keeps neighbouring tiles, which share most of their records,
+// under one L2.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+{
+    constexpr int kXcd = 8;
+    const int q = nblocks / kXcd, r = nblocks % kXcd;
+    const int x = bid % kXcd, i = bid / kXcd;
+    return x * q + min(x, r) + i;
+}
+
+// ------------------------------------------------------------- per-pixel coverage
+// Records of a batch sit in LDS as structure of arrays by float4 group: group g of
+// record j at lds4[g * B + j] (B = batch), so lanes that read different records touch
+// consecutive 16-byte slots.
+//
+// chunk_mask: lane t holds record c0 + t of a chunk of up to 64 (valid = t < count);
+// returns, for the calling lane's pixel (wx0 + lane % 8, wy0 + lane / 8), the 64-bit
+// mask of chunk records whose pixel box contains that pixel.  A box is separable into a
+// column range and a row range, so 8 ballots over column bits and 8 over row bits give
+// the whole 64 x 64 coverage matrix; lane p keeps column mask p % 8 AND row mask p / 8.
+// Outside the box alpha < alpha_min holds exactly (the box bounds both rho branches at
+// the alpha_min level), so skipping those pairs changes no result.
+__device__ __forceinline__ uint64_t chunk_mask(float4 head, bool valid, int wx0, int wy0,
+                                               int lane)
+{
+    uint32_t colbits = 0, rowbits = 0;
+    if (valid) {
+        const uint32_t x = __float_as_uint(head.x), y = __float_as_uint(head.y);
+        const int clo = max((int)(int16_t)(x & 0xFFFFu) - wx0, 0);
+        const int chi = min((int)(int16_t)(x >> 16) - wx0, 7);
+        const int rlo = max((int)(int16_t)(y & 0xFFFFu) - wy0, 0);
+        const int rhi = min((int)(int16_t)(y >> 16) - wy0, 7);
+        if (clo <= chi) colbits = (0xFFu >> (7 - chi)) & (0xFFu << clo);
+        if (rlo <= rhi) rowbits = (0xFFu >> (7 - rhi)) & (0xFFu << rlo);
+    }
+    const int lc = lane & 7, lr = lane >> 3;
+    uint64_t cm = 0, rm = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint64_t bc = __ballot((colbits >> c) & 1u);
+        const uint64_t br = __ballot((rowbits >> c) & 1u);
+        cm = lc == c ? bc : cm;
+        rm = lr == c ? br : rm;
+    }
+    return cm & rm;
+}
+
 // ---------------------------------------------------------------- raster forward
 // One block per tile (TS x TS threads, one pixel each); wave w owns an 8x8 sub-block.
-// Records of the tile list are staged in LDS in batches; each wave culls a record by
-// its pixel box against the wave's sub-block, then composites front to back; a wave
-// whose 64 pixels all saturated stops, the block stops when all waves have.
+// Records of the tile list are staged in LDS in batches (one record per thread, the
+// next batch prefetched into registers).  Per chunk of 64 staged records each lane
+// builds the mask of records covering its pixel and composites only those, front to
+// back, until its transmittance would drop below T_min; a wave whose 64 pixels all
+// stopped skips the rest, the block stops when all waves have.
 template <int TS, bool DEPTH_ONLY, bool HAS_VIS>
 __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
@@ -334,9 +384,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     unsigned long long *__restrict__ stats)
 {
     constexpr int NT = TS * TS;
-    constexpr int NV4 = DEPTH_ONLY ? 4 : kRecVec4;
     extern __shared__ float4 lds[];
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
     const ViewDesc vd = views[v];
     const int lt = tile - vd.tile_off;
@@ -352,55 +401,55 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     float Tr = 1.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, aV = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
     int lastpos = 0, ncontrib = 0, neval = 0;
     bool done = !inside;
-    // batch <= NT: one record per thread.  The next batch is fetched into registers
-    // (NV4 independent float4 loads per thread) while the current one is composited.
-    const int batch = min(rc.batch, NT);
-    float4 q[NV4];
-    auto fetch = [&](uint32_t base, int cnt) {
-        if (tid < cnt) {
-            const uint32_t idx = min(lists[base + tid], (uint32_t)(n - 1));
-            const float4 *src = recv + (size_t)idx * kRecVec4;
-#pragma unroll
-            for (int k = 0; k < NV4; ++k) q[k] = src[k];
-        }
-    };
-    if (start < end) fetch(start, (int)min((uint32_t)batch, end - start));
-    for (uint32_t b0 = start; b0 < end; b0 += batch) {
-        const int nb = (int)min((uint32_t)batch, end - b0);
+    const int B = min(rc.batch, NT);
+    float4 q0, q1, q2, q3, q4, q5;
+#define SS_FETCH_FWD(BASE, CNT)                                                        \
+    if (tid < (CNT)) {                                                                 \
+        const uint32_t idx_ = min(lists[(BASE) + tid], (uint32_t)(n - 1));             \
+        const float4 *src_ = recv + (size_t)idx_ * kRecVec4;                           \
+        q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3];                        \
+        if (!DEPTH_ONLY) { q4 = src_[4]; q5 = src_[5]; }                               \
+    }
+    if (start < end) { SS_FETCH_FWD(start, (int)min((uint32_t)B, end - start)); }
+    for (uint32_t b0 = start; b0 < end; b0 += B) {
+        const int nb = (int)min((uint32_t)B, end - b0);
         __syncthreads();
         if (tid < nb) {
-#pragma unroll
-            for (int k = 0; k < NV4; ++k) lds[tid * kRecVec4 + k] = q[k];
+            lds[tid] = q0; lds[B + tid] = q1; lds[2 * B + tid] = q2; lds[3 * B + tid] = q3;
+            if (!DEPTH_ONLY) { lds[4 * B + tid] = q4; lds[5 * B + tid] = q5; }
         }
         __syncthreads();
-        const uint32_t b1 = b0 + batch;
-        if (b1 < end) fetch(b1, (int)min((uint32_t)batch, end - b1));
-        if (__ballot(!done) != 0) {
-            float4 c0 = lds[0], c1 = lds[1], c2 = lds[2], c3 = lds[3];
-            for (int j = 0; j < nb; ++j) {
-                const float4 r0 = c0, r1 = c1, r2 = c2, r3 = c3;
-                if (j + 1 < nb) {   // next record's fields load while this one is evaluated
-                    const float4 *Rn = lds + (j + 1) * kRecVec4;
-                    c0 = Rn[0]; c1 = Rn[1]; c2 = Rn[2]; c3 = Rn[3];
-                }
-                // 8x8 tiles: the binning already guarantees the record overlaps the wave's
-                // pixels; larger tiles cull per 8x8 wave sub-block
-                if (TS > 8 && !box_hits(r0.x, r0.y, wx0, wy0)) continue;
-                if (__ballot(!done) == 0) break;
-                if (done) continue;
+        const uint32_t b1 = b0 + B;
+        if (b1 < end) { SS_FETCH_FWD(b1, (int)min((uint32_t)B, end - b1)); }
+        const int pos0 = (int)(b0 - start);
+        for (int c0 = 0; c0 < nb; c0 += 64) {
+            if (__ballot(!done) == 0) break;
+            const int cnt = min(64, nb - c0);
+            const float4 head = lds[c0 + (lane < cnt ? lane : 0)];
+            uint64_t m = chunk_mask(head, lane < cnt, wx0, wy0, lane);
+            if (done) m = 0;
+            // the next covered record's fields are read from LDS while this one is evaluated
+            int j = c0 + (m != 0 ? (int)__builtin_ctzll(m) : 0);
+            float4 c0r = lds[j], c1r = lds[B + j], c2r = lds[2 * B + j], c3r = lds[3 * B + j];
+            while (m != 0) {
+                m &= m - 1;
+                const int jc = j;
+                const float4 r0 = c0r, r1 = c1r, r2 = c2r, r3 = c3r;
+                j = c0 + (m != 0 ? (int)__builtin_ctzll(m) : 0);
+                c0r = lds[j]; c1r = lds[B + j]; c2r = lds[2 * B + j]; c3r = lds[3 * B + j];
                 ++neval;
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 if (e.alpha >= rc.alpha_min) {
                     const float Tn = __fmul_rn(Tr, __fsub_rn(1.f, e.alpha));
                     if (Tn < rc.T_min) {
                         done = true;
+                        m = 0;
                     } else {
                         const float w = __fmul_rn(e.alpha, Tr);
                         const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
                         aD = __fmaf_rn(w, z, aD);
                         if (!DEPTH_ONLY) {
-                            const float4 *R = lds + j * kRecVec4;
-                            const float4 r4 = R[4], r5 = R[5];
+                            const float4 r4 = lds[4 * B + jc], r5 = lds[5 * B + jc];
                             a0 = __fmaf_rn(w, r4.x, a0);
                             a1 = __fmaf_rn(w, r4.y, a1);
                             a2 = __fmaf_rn(w, r4.z, a2);
@@ -410,7 +459,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                             n2 = __fmaf_rn(w, r5.z, n2);
                         }
                         Tr = Tn;
-                        lastpos = (int)(b0 - start) + j + 1;
+                        lastpos = pos0 + jc + 1;
                         ++ncontrib;
                     }
                 }
@@ -418,6 +467,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
         }
         if (!__syncthreads_or(!done)) break;
     }
+#undef SS_FETCH_FWD
     {
         // work counters: one 64-bit atomic per wave and counter
         unsigned long long c = (unsigned long long)ncontrib, e = (unsigned long long)neval;
@@ -554,14 +604,53 @@ __device__ __forceinline__ float wave_transpose_reduce16(float (&x)[16], int lan
     return y;
 }
 
+// Within one 16-lane row: 16 per-lane values -> lane i holds the row sum of value i.
+// Four levels, each pairing lanes that differ in one index bit (row mirror: bit 3,
+// half-row mirror: bit 2, quad permutes: bits 1 and 0); every level keeps the half of
+// the vector selected by that bit and adds the partner's copy of it.
+__device__ __forceinline__ float row_transpose_reduce16(const float (&x)[16], int lane)
+{
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+    float y8[8], y4[4], y2[2];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        y8[k] = (b3 ? x[k + 8] : x[k]) + dpp<0x140>(b3 ? x[k] : x[k + 8]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        y4[k] = (b2 ? y8[k + 4] : y8[k]) + dpp<0x141>(b2 ? y8[k] : y8[k + 4]);
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        y2[k] = (b1 ? y4[k + 2] : y4[k]) + dpp<0x4E>(b1 ? y4[k] : y4[k + 2]);
+    return (b0 ? y2[1] : y2[0]) + dpp<0xB1>(b0 ? y2[0] : y2[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+// Maximum over the 16 lanes of a row (same four partner patterns).
+__device__ __forceinline__ int row_max(int v)
+{
+    v = max(v, dpp_i<0x140>(v));
+    v = max(v, dpp_i<0x141>(v));
+    v = max(v, dpp_i<0x4E>(v));
+    v = max(v, dpp_i<0xB1>(v));
+    return v;
+}
+
 // --------------------------------------------------------------- raster backward
 // Back to front over each pixel's contributors [0, last): transmittance before a
 // surfel is recovered as T_i = T_{i+1} / (1 - alpha_i) from T_final, the suffix
 // g . sum_{j>i} w_j f_j is accumulated on the way, and per pair
 //   dL/dalpha_i = T_i (g . f_i) - (g . S_i) / (1 - alpha_i)           (Eq. rasterization)
 // then through alpha = min(alpha_max, o G), G = exp(-rho/2), rho = |Q delta|^2 or
-// |delta|^2 / sigma^2, delta = x - c, z = z0 - k . u.  The 16 record-gradient values
-// are transpose-reduced over the wave and added with one 16-lane atomic.
+// |delta|^2 / sigma^2, delta = x - c, z = z0 - k . u.  Each 16-lane row of a wave owns a
+// 4x4 quadrant of the wave's 8x8 pixels and walks, back to front, only the staged records
+// whose box meets that quadrant (4 ballots per chunk of 64 give the row masks); the 16
+// record-gradient values are reduced within the row and added with one atomic per lane,
+// so one instruction carries the sums of up to four records.
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
 template <int TS, bool HAS_VIS>
@@ -581,7 +670,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
     uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + min(rc.batch, NT) * kRecVec4);
     __shared__ float red[NW][16];
     __shared__ int max_last;
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
     const ViewDesc vd = views[v];
     const int lt = tile - vd.tile_off;
@@ -589,7 +678,9 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int WPR = TS / 8;
     const int wx0 = tx * TS + (wave % WPR) * 8, wy0 = ty * TS + (wave / WPR) * 8;
-    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    // 16-lane row `quad` owns the 4x4 quadrant (quad & 1, quad >> 1) of the wave's block
+    const int quad = lane >> 4;
+    const int px = wx0 + 4 * (quad & 1) + (lane & 3), py = wy0 + 4 * (quad >> 1) + ((lane >> 2) & 3);
     const bool inside = px < vd.W && py < vd.H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const int64_t P = (int64_t)vd.W * vd.H;
@@ -657,100 +748,129 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
     const int batch = min(rc.batch, NT);
     const float two_is2 = 2.f * rc.inv_s2;
     const int blk_last = min(max_last, tile_len);   // a stale `last` cannot read past the list
+    // the row walks records up to the largest `last` among its 16 pixels
+    const int row_last = row_max(mylast);
     // one record per thread; the batch before the current one (back to front) is
     // fetched into registers while the current one is processed
-    float4 q[kRecVec4];
+    float4 q0, q1, q2, q3, q4, q5;
     uint32_t qidx = 0;
-    auto fetch = [&](int bb, int cnt) {
-        if (tid < cnt) {
-            qidx = min(lists[start + bb + tid], (uint32_t)(n - 1));
-            const float4 *src = recv + (size_t)qidx * kRecVec4;
-#pragma unroll
-            for (int k = 0; k < kRecVec4; ++k) q[k] = src[k];
-        }
-    };
+#define SS_FETCH_BWD(BB, CNT)                                                          \
+    if (tid < (CNT)) {                                                                 \
+        qidx = min(lists[start + (BB) + tid], (uint32_t)(n - 1));                      \
+        const float4 *src_ = recv + (size_t)qidx * kRecVec4;                           \
+        q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3]; q4 = src_[4]; q5 = src_[5]; \
+    }
     if (blk_last > 0) {
-        const int bb = blk_last > batch ? blk_last - batch : 0;
-        fetch(bb, blk_last - bb);
+        const int bb0 = blk_last > batch ? blk_last - batch : 0;
+        SS_FETCH_BWD(bb0, blk_last - bb0);
     }
     for (int bend = blk_last; bend > 0; bend -= batch) {
         const int bb = bend > batch ? bend - batch : 0;
         const int nb = bend - bb;
         __syncthreads();
         if (tid < nb) {
-#pragma unroll
-            for (int k = 0; k < kRecVec4; ++k) lds[tid * kRecVec4 + k] = q[k];
+            float4 *dst = lds + tid * kRecVec4;
+            dst[0] = q0; dst[1] = q1; dst[2] = q2; dst[3] = q3; dst[4] = q4; dst[5] = q5;
             lds_idx[tid] = qidx;
         }
         __syncthreads();
         if (bb > 0) {
             const int pb = bb > batch ? bb - batch : 0;
-            fetch(pb, bb - pb);
+            SS_FETCH_BWD(pb, bb - pb);
         }
-        float4 c0 = lds[(nb - 1) * kRecVec4], c1 = lds[(nb - 1) * kRecVec4 + 1];
-        float4 c2 = lds[(nb - 1) * kRecVec4 + 2], c3 = lds[(nb - 1) * kRecVec4 + 3];
-        for (int j = nb - 1; j >= 0; --j) {
-            const float4 r0 = c0, r1 = c1, r2 = c2, r3 = c3;
-            if (j > 0) {   // previous record's fields load while this one is processed
-                const float4 *Rp = lds + (j - 1) * kRecVec4;
-                c0 = Rp[0]; c1 = Rp[1]; c2 = Rp[2]; c3 = Rp[3];
+        for (int c0 = ((nb - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
+            const int cnt = min(64, nb - c0);
+            // lane t tests chunk record c0 + t against the wave's four 4x4 quadrants
+            uint32_t qbits = 0;
+            if (lane < cnt) {
+                const float4 h = lds[(c0 + lane) * kRecVec4];
+                const uint32_t x = __float_as_uint(h.x), y = __float_as_uint(h.y);
+                const int xlo = (int)(int16_t)(x & 0xFFFFu), xhi = (int)(int16_t)(x >> 16);
+                const int ylo = (int)(int16_t)(y & 0xFFFFu), yhi = (int)(int16_t)(y >> 16);
+                const bool c0h = xlo <= wx0 + 3 && xhi >= wx0, c1h = xlo <= wx0 + 7 && xhi >= wx0 + 4;
+                const bool r0h = ylo <= wy0 + 3 && yhi >= wy0, r1h = ylo <= wy0 + 7 && yhi >= wy0 + 4;
+                qbits = (uint32_t)(c0h && r0h) | ((uint32_t)(c1h && r0h) << 1) |
+                        ((uint32_t)(c0h && r1h) << 2) | ((uint32_t)(c1h && r1h) << 3);
             }
-            const int pos = bb + j;
-            if (TS > 8 && !box_hits(r0.x, r0.y, wx0, wy0)) continue;
-            float gr[16];
+            uint64_t m = 0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) gr[k] = 0.f;
-            bool contrib = false;
-            if (pos < mylast) {
-                const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
-                if (e.alpha >= rc.alpha_min) {
-                    contrib = true;
-                    const float4 *R = lds + j * kRecVec4;
-                    const float4 r4 = R[4], r5 = R[5];
-                    const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
-                    const float Tb = Tr * rom;
-                    const float w = e.alpha * Tb;
-                    const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
-                    float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
-                               gN1 * r5.y + gN2 * r5.z;
-                    if (HAS_VIS) gf += gV * r4.w;
-                    const float dal = Tb * gf - gS * rom;
-                    gS += w * gf;
-                    Tr = Tb;
-                    const float dz = w * gD;
-                    gr[G_AR] = w * gA0; gr[G_AG] = w * gA1; gr[G_AB] = w * gA2;
-                    gr[G_NX] = w * gN0; gr[G_NY] = w * gN1; gr[G_NZ] = w * gN2;
-                    gr[G_Z0] = dz;
-                    float dG = 0.f;
-                    if (e.oG < rc.alpha_max) {
-                        gr[G_O] = e.G * dal;
-                        dG = r3.x * dal;
-                    }
-                    const float drho = -0.5f * e.G * dG;
-                    float ddx, ddy;
-                    if (e.ub) {
-                        const float du0 = 2.f * e.u0 * drho - r3.z * dz;
-                        const float du1 = 2.f * e.u1 * drho - r3.w * dz;
-                        gr[G_KU] = -e.u0 * dz;
-                        gr[G_KV] = -e.u1 * dz;
-                        gr[G_Q00] = du0 * e.dx; gr[G_Q01] = du0 * e.dy;
-                        gr[G_Q10] = du1 * e.dx; gr[G_Q11] = du1 * e.dy;
-                        ddx = r2.x * du0 + r2.z * du1;
-                        ddy = r2.y * du0 + r2.w * du1;
-                    } else {
-                        ddx = two_is2 * e.dx * drho;
-                        ddy = two_is2 * e.dy * drho;
-                    }
-                    gr[G_CX] = -ddx;
-                    gr[G_CY] = -ddy;
-                }
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t bq = __ballot((qbits >> q) & 1u);
+                m = quad == q ? bq : m;
             }
-            if (__ballot(contrib) == 0) continue;
-            const float sum = wave_transpose_reduce16(gr, lane);
-            if ((lane & 3) == 0)
-                atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane >> 2), sum);
+            const int lim = row_last - (bb + c0);        // chunk records j < lim can contribute
+            m &= lim >= 64 ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
+            // row-uniform walk, highest position first; the next record's fields are read
+            // from LDS while this one is processed
+            int jl = m != 0 ? 63 - (int)__builtin_clzll(m) : 0;
+            const float4 *Rn = lds + (c0 + jl) * kRecVec4;
+            float4 c0r = Rn[0], c1r = Rn[1], c2r = Rn[2], c3r = Rn[3];
+            while (__ballot(m != 0) != 0) {
+                const bool act = m != 0;
+                const int j = c0 + jl;
+                const float4 r0 = c0r, r1 = c1r, r2 = c2r, r3 = c3r;
+                if (act) m &= ~(1ull << jl);
+                jl = m != 0 ? 63 - (int)__builtin_clzll(m) : 0;
+                Rn = lds + (c0 + jl) * kRecVec4;
+                c0r = Rn[0]; c1r = Rn[1]; c2r = Rn[2]; c3r = Rn[3];
+                float gr[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) gr[k] = 0.f;
+                bool contrib = false;
+                if (act && bb + j < mylast) {
+                    const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
+                    if (e.alpha >= rc.alpha_min) {
+                        contrib = true;
+                        const float4 *R = lds + j * kRecVec4;
+                        const float4 r4 = R[4], r5 = R[5];
+                        const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
+                        const float Tb = Tr * rom;
+                        const float w = e.alpha * Tb;
+                        const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+                        float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
+                                   gN1 * r5.y + gN2 * r5.z;
+                        if (HAS_VIS) gf += gV * r4.w;
+                        const float dal = Tb * gf - gS * rom;
+                        gS += w * gf;
+                        Tr = Tb;
+                        const float dz = w * gD;
+                        gr[G_AR] = w * gA0; gr[G_AG] = w * gA1; gr[G_AB] = w * gA2;
+                        gr[G_NX] = w * gN0; gr[G_NY] = w * gN1; gr[G_NZ] = w * gN2;
+                        gr[G_Z0] = dz;
+                        float dG = 0.f;
+                        if (e.oG < rc.alpha_max) {
+                            gr[G_O] = e.G * dal;
+                            dG = r3.x * dal;
+                        }
+                        const float drho = -0.5f * e.G * dG;
+                        float ddx, ddy;
+                        if (e.ub) {
+                            const float du0 = 2.f * e.u0 * drho - r3.z * dz;
+                            const float du1 = 2.f * e.u1 * drho - r3.w * dz;
+                            gr[G_KU] = -e.u0 * dz;
+                            gr[G_KV] = -e.u1 * dz;
+                            gr[G_Q00] = du0 * e.dx; gr[G_Q01] = du0 * e.dy;
+                            gr[G_Q10] = du1 * e.dx; gr[G_Q11] = du1 * e.dy;
+                            ddx = r2.x * du0 + r2.z * du1;
+                            ddy = r2.y * du0 + r2.w * du1;
+                        } else {
+                            ddx = two_is2 * e.dx * drho;
+                            ddy = two_is2 * e.dy * drho;
+                        }
+                        gr[G_CX] = -ddx;
+                        gr[G_CY] = -ddy;
+                    }
+                }
+                const uint64_t cb = __ballot(contrib);
+                if (cb == 0) continue;
+                const float sum = row_transpose_reduce16(gr, lane);
+                // lane i of a row holds value i of its record's 16-lane sum
+                if (((cb >> (quad * 16)) & 0xFFFFull) != 0)
+                    atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane & 15), sum);
+            }
         }
     }
+#undef SS_FETCH_BWD
 }
 
 template <int TS, bool HV>

@@ -30,8 +30,8 @@ class TrainConfig:
     train_seed: int = 2004
     eval_seed: int = 3004
     batch: int = 65_536
-    epochs: int = 3
-    lr: float = 3e-3
+    epochs: int = 30
+    lr: float = 1e-2
     band: float = 0.1
     chunk: int = 20            # suns per geometric-pass call
     init_seed: int = 0

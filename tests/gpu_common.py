@@ -41,6 +41,13 @@ def expand3(mask, W, H):
     return np.concatenate(out)
 
 
+# Gradients are FP32 sums whose order the hardware's float atomics decide (LDS and global).
+# Reordering a sum of K terms moves it by about sqrt(K) * 6e-8 * sum|x_i|; rel_err floors
+# its denominator at 1e-2 rms, so a nearly cancelling element can magnify that up to 100x.
+# Per-record K stays in the hundreds here: 1e-4 bounds run-to-run differences.
+ATOMIC_ORDER_TOL = 1e-4
+
+
 def rel_err(a, b):
     """max_i |a_i - b_i| / max(|b_i|, 1e-2 rms(b)): the per-tensor gradient metric."""
     a = np.asarray(a, np.float64).reshape(-1)

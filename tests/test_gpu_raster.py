@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import synth
-from gpu_common import (GRAD_KEYS, context, expand3, make_plan, oracle_settings, rel_err,
+from gpu_common import (ATOMIC_ORDER_TOL, GRAD_KEYS, context, expand3, make_plan, oracle_settings, rel_err,
                         to_np)
 
 pytestmark = pytest.mark.gpu
@@ -210,7 +210,7 @@ def test_forward_deterministic_backward_nearly():
     g1 = {k: to_np(v).copy() for k, v in plan.backward(surf, views, out, dI, dD, dN).items()}
     g2 = plan.backward(surf, views, out, dI, dD, dN)
     for k in GRAD_KEYS:
-        assert rel_err(to_np(g2[k]), g1[k]) < 1e-5, k
+        assert rel_err(to_np(g2[k]), g1[k]) < ATOMIC_ORDER_TOL, k
 
 
 def test_pair_count_scan_beyond_one_pass_of_the_partials_kernel():
