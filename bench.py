@@ -34,6 +34,37 @@ FLOPS_FWD_PAIR = 46
 FLOPS_BWD_PAIR = 90
 
 
+# HBM bytes per launch measured with the profiler's byte counters (FETCH_SIZE, WRITE_SIZE,
+# each scaled by what it reads for a plain copy of known size).  The record names the
+# digest of the kernel sources it was taken with; any change to them makes it stale and
+# `traffic` is then reported as null.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_c3_2M_40views_tile8_batch64.json")
+
+
+def kernel_source_digest(files):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in files:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, tile, batch):
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (rec.get("workload"), rec.get("tile"), rec.get("batch_depth")) != (workload, tile, batch):
+        return None
+    if kernel not in rec.get("kernels", {}):
+        return None
+    if rec.get("source_sha256") != kernel_source_digest(rec.get("source_files", [])):
+        return None
+    return rec["kernels"][kernel]["bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,8 +263,9 @@ def main():
     }
     dom = max(cands, key=lambda k: cands[k][1])
     achieved = cands[dom][0]
+    traffic = measured_traffic(dom, spec.name, plan.settings.tile_size, plan.settings.batch_depth)
     roofline = dict(kernel=dom, bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TFLOPS, 1),
-                    unit="TFLOP/s", frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=None,
+                    unit="TFLOP/s", frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=traffic,
                     avg_ms=round(cands[dom][1], 4),
                     work=f"{FLOPS_FWD_PAIR if dom == 'raster_fwd' else FLOPS_BWD_PAIR} flop x "
                          f"{C} contributing pairs per launch")
