@@ -162,8 +162,9 @@ def surrogate_eval(ctx, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU design shards views, see the design notes)"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (over "
+                                   "several GPUs the path would shard views and all-reduce the "
+                                   "surfel gradients once per step)"}))
         sys.exit(2)
     import numpy as np
     import torch

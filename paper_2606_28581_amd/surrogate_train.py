@@ -160,7 +160,7 @@ def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, 
         train_suns = draw_suns(cfg.train_suns, cfg.sun_elev_deg, cfg.train_seed)
     suns = draw_suns(cfg.eval_suns, cfg.sun_elev_deg, cfg.eval_seed, exclude=train_suns)
     sun_t = torch.as_tensor(suns, device=dev)
-    agree = agree_net = fallback = total = 0
+    agree = agree_net = fallback = total = lit = 0
     t_plain = t_sur = 0.0
     ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     plan = lab.plan
@@ -184,11 +184,12 @@ def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, 
         p = net.forward(w, lab.surf.mean, s.contiguous(), all_pairs=True, prob=True).view(lab.chunk, -1)
         agree += ((vis[:nv] >= 0.5) == (ref[:nv] >= 0.5)).sum().item()
         agree_net += ((p[:nv] >= 0.5) == (ref[:nv] >= 0.5)).sum().item()
+        lit += (ref[:nv] >= 0.5).sum().item()
         total += ref[:nv].numel()
     nviews = (cfg.eval_suns + lab.chunk - 1) // lab.chunk * lab.chunk
     res = dict(eval_suns=cfg.eval_suns, points=total,
                agreement=round(agree / total, 5), agreement_network_only=round(agree_net / total, 5),
-               fallback_fraction=round(fallback / total, 5),
+               fallback_fraction=round(fallback / total, 5), lit_fraction=round(lit / total, 5),
                plain_ms_per_view=round(t_plain / nviews, 4),
                surrogate_ms_per_view=round(t_sur / nviews, 4))
     log(f"[surrogate] eval: {res}")

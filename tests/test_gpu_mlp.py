@@ -134,3 +134,32 @@ def test_surrogate_shadow_falls_back_exactly(band):
     np.testing.assert_array_equal(vis[flagged], plain[flagged])
     np.testing.assert_allclose(vis[~flagged], p[~flagged], rtol=0, atol=0)
     assert plan.stats()["fallback"] == int(flagged.sum())
+
+
+def test_trained_surrogate_gains_over_the_plain_pass():
+    """What the learned part adds.  Trained on the geometric pass's own labels with the
+    library's kernels, the network decides most held-out (surfel, sun) pairs on its own,
+    so the sun raster runs only for the low-confidence rest; with that fallback its
+    lit/shadow decisions agree with the plain pass, and the bare network beats both the
+    untrained network and the best constant guess."""
+    from paper_2606_28581_amd import surrogate_train as st
+    spec = synth.tiny(n_surfels=3000, views=((32, 32),), extent=64.0, n_boxes=6, seed=41,
+                      box_height=(4.0, 16.0), box_side=(6.0, 14.0))
+    sc = synth.make_scene(spec)
+    surf, views = ss.scene_to_device(sc, with_sun=False)
+    zc = float(np.mean(sc["surfels"]["mean"][:, 2]))
+    net = sg.Mlp(context(), np.array([0.0, 0.0, zc], np.float32), np.float32(2.0 / spec.extent))
+    cfg = st.TrainConfig(train_suns=300, points_per_sun=2000, eval_suns=40, batch=8192,
+                         epochs=40, lr=1e-2, chunk=20)
+    lab = st.ShadowLab(context(), surf, views.Fxy, views.b_z, cfg.chunk, sun_map=256, tile=16)
+    quiet = lambda *a, **k: None
+    w, tr = st.train(lab, net, cfg, log=quiet)
+    ev = st.evaluate(lab, net, w, cfg, log=quiet)
+    w0 = torch.as_tensor(st.init_params(cfg.init_seed), device="cuda")
+    ev0 = st.evaluate(lab, net, w0, cfg, log=quiet)
+    const = max(ev["lit_fraction"], 1.0 - ev["lit_fraction"])
+    info = dict(trained=ev, untrained=ev0, best_constant=const, training=tr)
+    assert ev["agreement_network_only"] > const + 0.05, info
+    assert ev["agreement_network_only"] > ev0["agreement_network_only"] + 0.05, info
+    assert ev["fallback_fraction"] < 0.5, info
+    assert ev["agreement"] > 0.95, info
