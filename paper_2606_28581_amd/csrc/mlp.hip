@@ -183,12 +183,15 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(
     __shared__ MlpLds L;
     load_weights(L, wb, wf);
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u16 *H0 = L.H[wave][0], *H1 = L.H[wave][1];
     const int64_t ntile = (M + kPtsPerWave - 1) / kPtsPerWave;
     for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
          tile += (int64_t)gridDim.x * kMlpWaves) {
         const int64_t base = tile * kPtsPerWave;
+        // all-pairs mode: one division per tile; lanes carry into the next sun
+        const int64_t is0 = G > 0 ? base / G : 0, ip0 = base - is0 * G;
         // ---- features in operand layout
         Frag fa[2][4];
 #pragma unroll
@@ -196,7 +199,12 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(
             int64_t i = base + rt * 16 + (lane & 15);
             const bool valid = i < M;
             if (!valid) i = M - 1;
-            const int64_t ip = G > 0 ? i % G : i, is = G > 0 ? i / G : i;
+            int64_t ip = i, is = i;
+            if (G > 0) {
+                ip = ip0 + (i - base);
+                is = is0;
+                while (ip >= G) { ip -= G; ++is; }
+            }
             float ph[3];
             ph[0] = __fmul_rn(__fsub_rn(pts[3 * ip], nz.cx), nz.inv_half);
             ph[1] = __fmul_rn(__fsub_rn(pts[3 * ip + 1], nz.cy), nz.inv_half);

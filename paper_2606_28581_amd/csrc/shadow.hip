@@ -161,29 +161,84 @@ hipError_t launch_shadow_query(const float *mean, int64_t n, int32_t nv, const S
 
 // Surrogate fallback: every point whose surrogate visibility lies within `band` of 0.5
 // marks the sun-map tiles of its 3x3 texel window (same FP64 texel choice as the query)
-// and is counted.
-__global__ void k_flag_tiles(const float *__restrict__ mean, int64_t n,
-                             const SunCam *__restrict__ sun, const ViewDesc *__restrict__ views,
-                             int32_t S, int ts, const float *__restrict__ vis, float band,
-                             uint32_t *__restrict__ tmask, unsigned long long *__restrict__ count)
+// and is counted.  A block covers a contiguous chunk of one view's points and collects
+// the view's tile set as a bitmask in LDS (the window spans at most 2 x 2 tiles); at the
+// end it stores its set tiles with coalesced writes and adds its count with one atomic.
+constexpr int kFlagThreads = 256;
+constexpr int kFlagChunk = 8192;         // points per block
+
+__global__ __launch_bounds__(kFlagThreads) void k_flag_tiles(
+    const float *__restrict__ mean, int64_t n, const SunCam *__restrict__ sun,
+    const ViewDesc *__restrict__ views, int32_t S, int ts, const float *__restrict__ vis,
+    float band, uint32_t *__restrict__ tmask, unsigned long long *__restrict__ count)
+{
+    extern __shared__ uint32_t bits[];
+    __shared__ uint32_t nflag;
+    const int v = blockIdx.y;
+    const ViewDesc vd = views[v];
+    const int ntiles = vd.tiles_x * vd.tiles_y;
+    const int nwords = (ntiles + 31) >> 5;
+    for (int i = threadIdx.x; i < nwords; i += kFlagThreads) bits[i] = 0u;
+    if (threadIdx.x == 0) nflag = 0u;
+    __syncthreads();
+    const SunCam &c = sun[v];
+    const int64_t k0 = (int64_t)blockIdx.x * kFlagChunk;
+    const int64_t k1 = min(n, k0 + (int64_t)kFlagChunk);
+    uint32_t mine = 0;
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += kFlagThreads) {
+        if (!(fabsf(vis[(int64_t)v * n + k] - 0.5f) < band)) continue;
+        ++mine;
+        const double p0 = mean[3 * k], p1 = mean[3 * k + 1], p2 = mean[3 * k + 2];
+        double x = c.b[0], y = c.b[1];
+        x += c.B[0] * p0; x += c.B[1] * p1; x += c.B[2] * p2;
+        y += c.B[3] * p0; y += c.B[4] * p1; y += c.B[5] * p2;
+        const double fx = floor(x), fy = floor(y);
+        // texel window [fx - 1, fx + 1] x [fy - 1, fy + 1] clipped to the map
+        const double xl = fmax(fx - 1.0, 0.0), xh = fmin(fx + 1.0, (double)(S - 1));
+        const double yl = fmax(fy - 1.0, 0.0), yh = fmin(fy + 1.0, (double)(S - 1));
+        if (!(xl <= xh && yl <= yh)) continue;
+        const int cx0 = (int)xl / ts, cx1 = (int)xh / ts, cy0 = (int)yl / ts, cy1 = (int)yh / ts;
+        for (int ty = cy0; ty <= cy1; ++ty)
+            for (int tx = cx0; tx <= cx1; ++tx) {
+                const int t = ty * vd.tiles_x + tx;
+                atomicOr(&bits[t >> 5], 1u << (t & 31));
+            }
+    }
+    if (mine) atomicAdd(&nflag, mine);
+    __syncthreads();
+    for (int t = threadIdx.x; t < ntiles; t += kFlagThreads)
+        if ((bits[t >> 5] >> (t & 31)) & 1u) tmask[vd.tile_off + t] = 1u;
+    if (threadIdx.x == 0 && nflag) atomicAdd(count, (unsigned long long)nflag);
+}
+
+// Same marking without the LDS bitmask, one point per thread, for sun maps whose tile
+// set does not fit in LDS.
+__global__ void k_flag_tiles_direct(const float *__restrict__ mean, int64_t n,
+                                    const SunCam *__restrict__ sun,
+                                    const ViewDesc *__restrict__ views, int32_t S, int ts,
+                                    const float *__restrict__ vis, float band,
+                                    uint32_t *__restrict__ tmask,
+                                    unsigned long long *__restrict__ count)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
-    if (k >= n) return;
-    if (!(fabsf(vis[(int64_t)v * n + k] - 0.5f) < band)) return;
-    atomicAdd(count, 1ull);
+    const bool flag = k < n && fabsf(vis[(int64_t)v * n + k] - 0.5f) < band;
+    const unsigned long long wb = __ballot(flag);
+    if ((threadIdx.x & 63) == 0 && wb != 0ull) atomicAdd(count, (unsigned long long)__popcll(wb));
+    if (!flag) return;
     const SunCam &c = sun[v];
     const double p0 = mean[3 * k], p1 = mean[3 * k + 1], p2 = mean[3 * k + 2];
     double x = c.b[0], y = c.b[1];
     x += c.B[0] * p0; x += c.B[1] * p1; x += c.B[2] * p2;
     y += c.B[3] * p0; y += c.B[4] * p1; y += c.B[5] * p2;
     const double fx = floor(x), fy = floor(y);
+    const double xl = fmax(fx - 1.0, 0.0), xh = fmin(fx + 1.0, (double)(S - 1));
+    const double yl = fmax(fy - 1.0, 0.0), yh = fmin(fy + 1.0, (double)(S - 1));
+    if (!(xl <= xh && yl <= yh)) return;
     const ViewDesc vd = views[v];
-    for (int t = 0; t < 9; ++t) {
-        const double tx = fx + (t % 3) - 1, ty = fy + (t / 3) - 1;
-        if (tx >= 0 && ty >= 0 && tx < S && ty < S)
-            tmask[vd.tile_off + ((int)ty / ts) * vd.tiles_x + ((int)tx / ts)] = 1u;
-    }
+    const int cx0 = (int)xl / ts, cx1 = (int)xh / ts, cy0 = (int)yl / ts, cy1 = (int)yh / ts;
+    for (int ty = cy0; ty <= cy1; ++ty)
+        for (int tx = cx0; tx <= cx1; ++tx) tmask[vd.tile_off + ty * vd.tiles_x + tx] = 1u;
 }
 
 hipError_t launch_flag_tiles(const float *mean, int64_t n, int32_t nv, const SunCam *sun,
@@ -191,8 +246,16 @@ hipError_t launch_flag_tiles(const float *mean, int64_t n, int32_t nv, const Sun
                              float band, uint32_t *tmask, unsigned long long *count, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0,
-                       st, mean, n, sun, views, S, ts, vis, band, tmask, count);
+    const int64_t tiles = (int64_t)((S + ts - 1) / ts) * ((S + ts - 1) / ts);
+    const size_t lds = (size_t)((tiles + 31) / 32) * sizeof(uint32_t);
+    if (lds > 48 * 1024) {                               // sun maps above 4096^2 at 8x8 tiles
+        hipLaunchKernelGGL(k_flag_tiles_direct, dim3((unsigned)((n + 255) / 256), (unsigned)nv),
+                           dim3(256), 0, st, mean, n, sun, views, S, ts, vis, band, tmask, count);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_flag_tiles, dim3((unsigned)((n + kFlagChunk - 1) / kFlagChunk), (unsigned)nv),
+                       dim3(kFlagThreads), lds, st, mean, n, sun, views, S, ts, vis, band, tmask,
+                       count);
     return hipGetLastError();
 }
 
