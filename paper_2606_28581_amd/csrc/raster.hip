@@ -439,30 +439,30 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                 c0r = lds[j]; c1r = lds[B + j]; c2r = lds[2 * B + j]; c3r = lds[3 * B + j];
                 ++neval;
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
-                if (e.alpha >= rc.alpha_min) {
-                    const float Tn = __fmul_rn(Tr, __fsub_rn(1.f, e.alpha));
-                    if (Tn < rc.T_min) {
-                        done = true;
-                        m = 0;
-                    } else {
-                        const float w = __fmul_rn(e.alpha, Tr);
-                        const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
-                        aD = __fmaf_rn(w, z, aD);
-                        if (!DEPTH_ONLY) {
-                            const float4 r4 = lds[4 * B + jc], r5 = lds[5 * B + jc];
-                            a0 = __fmaf_rn(w, r4.x, a0);
-                            a1 = __fmaf_rn(w, r4.y, a1);
-                            a2 = __fmaf_rn(w, r4.z, a2);
-                            if (HAS_VIS) aV = __fmaf_rn(w, r4.w, aV);
-                            n0 = __fmaf_rn(w, r5.x, n0);
-                            n1 = __fmaf_rn(w, r5.y, n1);
-                            n2 = __fmaf_rn(w, r5.z, n2);
-                        }
-                        Tr = Tn;
-                        lastpos = pos0 + jc + 1;
-                        ++ncontrib;
-                    }
+                // branch-free: a skipped pair accumulates with weight 0 (w * x + a == a
+                // exactly for the finite record fields), so no exec-mask juggling per pair
+                const bool hit = e.alpha >= rc.alpha_min;
+                const float Tn = __fmul_rn(Tr, __fsub_rn(1.f, e.alpha));
+                const bool stop = hit && Tn < rc.T_min;
+                const bool take = hit && !stop;
+                const float w = take ? __fmul_rn(e.alpha, Tr) : 0.f;
+                const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+                aD = __fmaf_rn(w, z, aD);
+                if (!DEPTH_ONLY) {
+                    const float4 r4 = lds[4 * B + jc], r5 = lds[5 * B + jc];
+                    a0 = __fmaf_rn(w, r4.x, a0);
+                    a1 = __fmaf_rn(w, r4.y, a1);
+                    a2 = __fmaf_rn(w, r4.z, a2);
+                    if (HAS_VIS) aV = __fmaf_rn(w, r4.w, aV);
+                    n0 = __fmaf_rn(w, r5.x, n0);
+                    n1 = __fmaf_rn(w, r5.y, n1);
+                    n2 = __fmaf_rn(w, r5.z, n2);
                 }
+                Tr = take ? Tn : Tr;
+                lastpos = take ? pos0 + jc + 1 : lastpos;
+                ncontrib += take ? 1 : 0;
+                done = done || stop;
+                m = stop ? 0ull : m;
             }
         }
         if (!__syncthreads_or(!done)) break;
@@ -654,7 +654,7 @@ __device__ __forceinline__ int row_max(int v)
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
 template <int TS, bool HAS_VIS>
-__global__ __launch_bounds__(TS *TS) void k_raster_bwd(
+__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 5 : 4))) void k_raster_bwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
     RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
@@ -813,54 +813,44 @@ __global__ __launch_bounds__(TS *TS) void k_raster_bwd(
                 jl = m != 0 ? 63 - (int)__builtin_clzll(m) : 0;
                 Rn = lds + (c0 + jl) * kRecVec4;
                 c0r = Rn[0]; c1r = Rn[1]; c2r = Rn[2]; c3r = Rn[3];
+                // branch-free: every lane evaluates the row's record; lanes that do not
+                // contribute (outside [0, last) or alpha < alpha_min) get zero gradients
+                // and leave T and the suffix unchanged
+                const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
+                const bool contrib = act && bb + j < mylast && e.alpha >= rc.alpha_min;
+                const float4 *R = lds + j * kRecVec4;
+                const float4 r4 = R[4], r5 = R[5];
+                const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
+                const float Tb = Tr * rom;
+                const float w = contrib ? e.alpha * Tb : 0.f;
+                const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+                float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
+                           gN1 * r5.y + gN2 * r5.z;
+                if (HAS_VIS) gf += gV * r4.w;
+                const float dal = contrib ? Tb * gf - gS * rom : 0.f;
+                gS += w * gf;
+                Tr = contrib ? Tb : Tr;
+                const float dz = w * gD;
                 float gr[16];
-#pragma unroll
-                for (int k = 0; k < 16; ++k) gr[k] = 0.f;
-                bool contrib = false;
-                if (act && bb + j < mylast) {
-                    const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
-                    if (e.alpha >= rc.alpha_min) {
-                        contrib = true;
-                        const float4 *R = lds + j * kRecVec4;
-                        const float4 r4 = R[4], r5 = R[5];
-                        const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
-                        const float Tb = Tr * rom;
-                        const float w = e.alpha * Tb;
-                        const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
-                        float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
-                                   gN1 * r5.y + gN2 * r5.z;
-                        if (HAS_VIS) gf += gV * r4.w;
-                        const float dal = Tb * gf - gS * rom;
-                        gS += w * gf;
-                        Tr = Tb;
-                        const float dz = w * gD;
-                        gr[G_AR] = w * gA0; gr[G_AG] = w * gA1; gr[G_AB] = w * gA2;
-                        gr[G_NX] = w * gN0; gr[G_NY] = w * gN1; gr[G_NZ] = w * gN2;
-                        gr[G_Z0] = dz;
-                        float dG = 0.f;
-                        if (e.oG < rc.alpha_max) {
-                            gr[G_O] = e.G * dal;
-                            dG = r3.x * dal;
-                        }
-                        const float drho = -0.5f * e.G * dG;
-                        float ddx, ddy;
-                        if (e.ub) {
-                            const float du0 = 2.f * e.u0 * drho - r3.z * dz;
-                            const float du1 = 2.f * e.u1 * drho - r3.w * dz;
-                            gr[G_KU] = -e.u0 * dz;
-                            gr[G_KV] = -e.u1 * dz;
-                            gr[G_Q00] = du0 * e.dx; gr[G_Q01] = du0 * e.dy;
-                            gr[G_Q10] = du1 * e.dx; gr[G_Q11] = du1 * e.dy;
-                            ddx = r2.x * du0 + r2.z * du1;
-                            ddy = r2.y * du0 + r2.w * du1;
-                        } else {
-                            ddx = two_is2 * e.dx * drho;
-                            ddy = two_is2 * e.dy * drho;
-                        }
-                        gr[G_CX] = -ddx;
-                        gr[G_CY] = -ddy;
-                    }
-                }
+                gr[G_AR] = w * gA0; gr[G_AG] = w * gA1; gr[G_AB] = w * gA2;
+                gr[G_NX] = w * gN0; gr[G_NY] = w * gN1; gr[G_NZ] = w * gN2;
+                gr[G_Z0] = dz;
+                const bool unclamped = e.oG < rc.alpha_max;
+                gr[G_O] = unclamped ? e.G * dal : 0.f;
+                const float dG = unclamped ? r3.x * dal : 0.f;
+                const float drho = -0.5f * e.G * dG;
+                const float du0 = 2.f * e.u0 * drho - r3.z * dz;
+                const float du1 = 2.f * e.u1 * drho - r3.w * dz;
+                gr[G_KU] = e.ub ? -e.u0 * dz : 0.f;
+                gr[G_KV] = e.ub ? -e.u1 * dz : 0.f;
+                gr[G_Q00] = e.ub ? du0 * e.dx : 0.f;
+                gr[G_Q01] = e.ub ? du0 * e.dy : 0.f;
+                gr[G_Q10] = e.ub ? du1 * e.dx : 0.f;
+                gr[G_Q11] = e.ub ? du1 * e.dy : 0.f;
+                const float ddx = e.ub ? r2.x * du0 + r2.z * du1 : two_is2 * e.dx * drho;
+                const float ddy = e.ub ? r2.y * du0 + r2.w * du1 : two_is2 * e.dy * drho;
+                gr[G_CX] = -ddx;
+                gr[G_CY] = -ddy;
                 const uint64_t cb = __ballot(contrib);
                 if (cb == 0) continue;
                 const float sum = row_transpose_reduce16(gr, lane);
