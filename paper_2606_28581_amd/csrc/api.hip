@@ -54,7 +54,7 @@ struct Layout {
     size_t rec_main, tiles_main, counts_main, offs_main, scanparts;
     size_t pk_a, pv_a, pk_b, pv_b, ranges_main, recgrad, colour_parts, dF_parts;
     size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
-    size_t sun_depth, bounds, radix_temp, tmask_sun;
+    size_t sun_depth, bounds, radix_temp, tmask_sun, cmask, cmask_bytes;
     size_t total;
 };
 
@@ -201,6 +201,9 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.bounds = take((size_t)bounds_blocks(p->n) * 6 * 8);
     L.radix_temp = take(radix_temp_bytes(std::max<int64_t>(p->n, std::max(cm, cs))));
     L.tmask_sun = take((size_t)p->tiles_sun_max * 4);
+    // forward -> backward contributor masks of 8x8 tiles (other sizes use the box test)
+    L.cmask_bytes = p->st.tile_size == 8 ? cmask_words(cm, p->tiles_main_max) * 8 : 0;
+    L.cmask = take(L.cmask_bytes);
     L.total = o;
     return L;
 }
@@ -322,6 +325,15 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
                          p->at<uint32_t>(sun ? L.ranges_sun : L.ranges_main), st));
     if (sun) p->lists_sun = lists; else p->lists_main = lists;
     return SS_OK;
+}
+
+// Contributor masks exist for 8x8 tiles when the workspace was laid out for them at the
+// current pair capacity (a tile-size change keeps the layout: then the box test is used).
+static unsigned long long *cmask_ptr(const ss_plan *p)
+{
+    if (p->st.tile_size != 8 || p->L.cmask_bytes < cmask_words(p->cap_main, p->tiles_main_max) * 8)
+        return nullptr;
+    return p->at<unsigned long long>(p->L.cmask);
 }
 
 static ss_status upload_views(ss_plan *p)
@@ -576,7 +588,7 @@ ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const f
                                  p->at<uint32_t>(p->L.ranges_main), p->lists_main,
                                  p->at<float>(p->L.rec_main), p->n, rc, v->colC, v->colc,
                                  v->ambient, nullptr, image, albedo_out, vis_out, depth, normal,
-                                 T_final, last, counters + 2, st));
+                                 T_final, last, counters + 2, cmask_ptr(p), st));
     }
     p->order_main = order;
     p->fwd_valid = true;
@@ -612,7 +624,8 @@ ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
                                  p->at<ViewDesc>(L.views_main), p->at<uint32_t>(L.ranges_main),
                                  p->lists_main, p->at<float>(L.rec_main), p->n, rc, v->colC,
                                  v->colc, v->ambient, albedo_out, vis_out, T_final, last, d_image,
-                                 d_depth, d_normal, recgrad, p->at<float>(L.colour_parts), st));
+                                 d_depth, d_normal, recgrad, p->at<float>(L.colour_parts),
+                                 cmask_ptr(p), st));
     }
     {
         StageScope scope(p, SS_STAGE_REDUCE, st);
@@ -661,7 +674,7 @@ ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, fl
                                  p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
                                  p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
                                  nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
-                                 nullptr, nullptr, nullptr, counters + 4, st));
+                                 nullptr, nullptr, nullptr, counters + 4, nullptr, st));
     }
     {
         StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);
@@ -1060,7 +1073,7 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
                                  p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
                                  p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
                                  nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
-                                 nullptr, nullptr, nullptr, counters + 4, st));
+                                 nullptr, nullptr, nullptr, counters + 4, nullptr, st));
     }
     {
         StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);

@@ -381,9 +381,12 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     const float *__restrict__ amb, const SunCam *__restrict__ sun, float *__restrict__ image,
     float *__restrict__ Aout, float *__restrict__ Vout, float *__restrict__ Dout,
     float *__restrict__ Nout, float *__restrict__ Tout, int32_t *__restrict__ lastout,
-    unsigned long long *__restrict__ stats)
+    unsigned long long *__restrict__ stats, unsigned long long *__restrict__ cmask)
 {
     constexpr int NT = TS * TS;
+    // 8x8 view passes record, per pixel and 64-position word of the tile list, which
+    // records it composited (the backward walks only those)
+    constexpr bool CM = TS == 8 && !DEPTH_ONLY;
     extern __shared__ float4 lds[];
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
@@ -411,6 +414,9 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
         if (!DEPTH_ONLY) { q4 = src_[4]; q5 = src_[5]; }                               \
     }
     if (start < end) { SS_FETCH_FWD(start, (int)min((uint32_t)B, end - start)); }
+    const size_t wbase = (size_t)(start >> 6) + (size_t)tile;   // tiles' word ranges are disjoint
+    unsigned long long wacc = 0ull;
+    int wcur = -1;
     for (uint32_t b0 = start; b0 < end; b0 += B) {
         const int nb = (int)min((uint32_t)B, end - b0);
         __syncthreads();
@@ -428,6 +434,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
             const float4 head = lds[c0 + (lane < cnt ? lane : 0)];
             uint64_t m = chunk_mask(head, lane < cnt, wx0, wy0, lane);
             if (done) m = 0;
+            unsigned long long cmc = 0ull;
             // the next covered record's fields are read from LDS while this one is evaluated
             int j = c0 + (m != 0 ? (int)__builtin_ctzll(m) : 0);
             float4 c0r = lds[j], c1r = lds[B + j], c2r = lds[2 * B + j], c3r = lds[3 * B + j];
@@ -458,15 +465,26 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                     n1 = __fmaf_rn(w, r5.y, n1);
                     n2 = __fmaf_rn(w, r5.z, n2);
                 }
+                if (CM) cmc |= take ? 1ull << (jc - c0) : 0ull;
                 Tr = take ? Tn : Tr;
                 lastpos = take ? pos0 + jc + 1 : lastpos;
                 ncontrib += take ? 1 : 0;
                 done = done || stop;
                 m = stop ? 0ull : m;
             }
+            if (CM && cmask) {
+                const int P0 = pos0 + c0, w = P0 >> 6;
+                if (w != wcur) {
+                    if (wcur >= 0) cmask[(wbase + wcur) * 64 + tid] = wacc;
+                    wacc = 0ull;
+                    wcur = w;
+                }
+                wacc |= cmc << (P0 & 63);
+            }
         }
         if (!__syncthreads_or(!done)) break;
     }
+    if (CM && cmask && wcur >= 0) cmask[(wbase + wcur) * 64 + tid] = wacc;
 #undef SS_FETCH_FWD
     {
         // work counters: one 64-bit atomic per wave and counter
@@ -514,11 +532,17 @@ static void launch_fwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const float *rec, int64_t n, const RasterConsts &rc,
                          const float *colC, const float *colc, const float *amb,
                          const SunCam *sun, float *image, float *A, float *V, float *D,
-                         float *N, float *T, int32_t *last, unsigned long long *stats)
+                         float *N, float *T, int32_t *last, unsigned long long *stats,
+                         unsigned long long *cmask)
 {
     hipLaunchKernelGGL((k_raster_fwd<TS, DO, HV>), grid, dim3(TS * TS), lds, st, nv, views,
                        ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
-                       amb, sun, image, A, V, D, N, T, last, stats);
+                       amb, sun, image, A, V, D, N, T, last, stats, cmask);
+}
+
+size_t cmask_words(int64_t pair_cap, int32_t tiles)
+{
+    return ((size_t)(pair_cap > 0 ? pair_cap : 0) / 64 + (size_t)(tiles > 0 ? tiles : 0) + 1) * 64;
 }
 
 hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
@@ -527,7 +551,7 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
                              const RasterConsts &rc, const float *colC, const float *colc,
                              const float *amb, const SunCam *sun, float *image, float *A,
                              float *V, float *D, float *N, float *T, int32_t *last,
-                             unsigned long long *stats, hipStream_t st)
+                             unsigned long long *stats, unsigned long long *cmask, hipStream_t st)
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
@@ -536,13 +560,13 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
     if (ts == TS_) {                                                                             \
         if (depth_only)                                                                          \
             launch_fwd_t<TS_, true, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
-                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats);\
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask);\
         else if (has_vis)                                                                        \
             launch_fwd_t<TS_, false, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
-                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats);\
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask);\
         else                                                                                     \
             launch_fwd_t<TS_, false, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,  \
-                                            colC, colc, amb, sun, image, A, V, D, N, T, last, stats);\
+                                            colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask);\
     }
     SS_FWD(8) else SS_FWD(16) else SS_FWD(32) else return hipErrorInvalidValue;
 #undef SS_FWD
@@ -630,6 +654,17 @@ __device__ __forceinline__ int dpp_i(int v)
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
+// OR of a 64-bit mask over the 16 lanes of a row (same four partner patterns).
+__device__ __forceinline__ uint64_t row_or64(uint64_t v)
+{
+    int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+    lo |= dpp_i<0x140>(lo); hi |= dpp_i<0x140>(hi);
+    lo |= dpp_i<0x141>(lo); hi |= dpp_i<0x141>(hi);
+    lo |= dpp_i<0x4E>(lo); hi |= dpp_i<0x4E>(hi);
+    lo |= dpp_i<0xB1>(lo); hi |= dpp_i<0xB1>(hi);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
 // Maximum over the 16 lanes of a row (same four partner patterns).
 __device__ __forceinline__ int row_max(int v)
 {
@@ -654,7 +689,7 @@ __device__ __forceinline__ int row_max(int v)
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
 template <int TS, bool HAS_VIS>
-__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 5 : 4))) void k_raster_bwd(
+__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 && HAS_VIS ? 5 : 4))) void k_raster_bwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
     RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
@@ -662,7 +697,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     const float *__restrict__ Vin, const float *__restrict__ Tin,
     const int32_t *__restrict__ lastin, const float *__restrict__ dI,
     const float *__restrict__ dD, const float *__restrict__ dN, float *__restrict__ recgrad,
-    float *__restrict__ colour_partials)
+    float *__restrict__ colour_partials, const unsigned long long *__restrict__ cmask)
 {
     constexpr int NT = TS * TS;
     constexpr int NW = NT / 64;
@@ -760,13 +795,19 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
         const float4 *src_ = recv + (size_t)qidx * kRecVec4;                           \
         q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3]; q4 = src_[4]; q5 = src_[5]; \
     }
-    if (blk_last > 0) {
-        const int bb0 = blk_last > batch ? blk_last - batch : 0;
+    // batches on the forward's grid ([k * batch, (k + 1) * batch) from the list start),
+    // back to front; the first one is cut at the tile's largest `last`
+    const bool use_cm = TS == 8 && cmask != nullptr;
+    const size_t wbase = (size_t)(start >> 6) + (size_t)tile;
+    const int pidx = ((py - wy0) << 3) | (px - wx0);   // the forward's lane of this pixel
+    const int nbat = (blk_last + batch - 1) / batch;
+    if (nbat > 0) {
+        const int bb0 = (nbat - 1) * batch;
         SS_FETCH_BWD(bb0, blk_last - bb0);
     }
-    for (int bend = blk_last; bend > 0; bend -= batch) {
-        const int bb = bend > batch ? bend - batch : 0;
-        const int nb = bend - bb;
+    for (int kb = nbat - 1; kb >= 0; --kb) {
+        const int bb = kb * batch;
+        const int nb = min(bb + batch, blk_last) - bb;
         __syncthreads();
         if (tid < nb) {
             float4 *dst = lds + tid * kRecVec4;
@@ -774,12 +815,17 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
             lds_idx[tid] = qidx;
         }
         __syncthreads();
-        if (bb > 0) {
-            const int pb = bb > batch ? bb - batch : 0;
-            SS_FETCH_BWD(pb, bb - pb);
-        }
+        if (kb > 0) SS_FETCH_BWD(bb - batch, batch);
         for (int c0 = ((nb - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
             const int cnt = min(64, nb - c0);
+            uint64_t m = 0;
+            if (use_cm) {
+                // the row walks the records any of its 16 pixels composited in the forward
+                const int P0 = bb + c0;
+                uint64_t cb = inside ? cmask[(wbase + (P0 >> 6)) * 64 + pidx] >> (P0 & 63) : 0ull;
+                cb &= cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+                m = row_or64(cb);
+            } else {
             // lane t tests chunk record c0 + t against the wave's four 4x4 quadrants
             uint32_t qbits = 0;
             if (lane < cnt) {
@@ -792,11 +838,11 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 qbits = (uint32_t)(c0h && r0h) | ((uint32_t)(c1h && r0h) << 1) |
                         ((uint32_t)(c0h && r1h) << 2) | ((uint32_t)(c1h && r1h) << 3);
             }
-            uint64_t m = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint64_t bq = __ballot((qbits >> q) & 1u);
                 m = quad == q ? bq : m;
+            }
             }
             const int lim = row_last - (bb + c0);        // chunk records j < lim can contribute
             m &= lim >= 64 ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
@@ -870,11 +916,11 @@ static void launch_bwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const float *colC, const float *colc, const float *amb,
                          const float *A, const float *V, const float *T, const int32_t *last,
                          const float *dI, const float *dD, const float *dN, float *recgrad,
-                         float *cp)
+                         float *cp, const unsigned long long *cmask)
 {
     hipLaunchKernelGGL((k_raster_bwd<TS, HV>), grid, dim3(TS * TS), lds, st, nv, views, ranges,
                        lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc, amb, A,
-                       V, T, last, dI, dD, dN, recgrad, cp);
+                       V, T, last, dI, dD, dN, recgrad, cp, cmask);
 }
 
 hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
@@ -884,7 +930,8 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
                              const float *amb, const float *A, const float *V,
                              const float *T, const int32_t *last, const float *dI,
                              const float *dD, const float *dN, float *recgrad,
-                             float *colour_partials, hipStream_t st)
+                             float *colour_partials, const unsigned long long *cmask,
+                             hipStream_t st)
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
@@ -894,11 +941,11 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
         if (has_vis)                                                                         \
             launch_bwd_t<TS_, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,      \
                                     colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad,     \
-                                    colour_partials);                                        \
+                                    colour_partials, cmask);                                 \
         else                                                                                 \
             launch_bwd_t<TS_, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,     \
                                      colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad,    \
-                                     colour_partials);                                       \
+                                     colour_partials, cmask);                                \
     }
     SS_BWD(8) else SS_BWD(16) else SS_BWD(32) else return hipErrorInvalidValue;
 #undef SS_BWD

@@ -111,7 +111,7 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
                              const RasterConsts &rc, const float *colC, const float *colc,
                              const float *amb, const SunCam *sun, float *image, float *A,
                              float *V, float *D, float *N, float *T, int32_t *last,
-                             unsigned long long *stats, hipStream_t st);
+                             unsigned long long *stats, unsigned long long *cmask, hipStream_t st);
 hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
                              const ViewDesc *views, const uint32_t *ranges,
                              const uint32_t *lists, const float *rec, int64_t n,
@@ -119,7 +119,12 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
                              const float *amb, const float *A, const float *V,
                              const float *T, const int32_t *last, const float *dI,
                              const float *dD, const float *dN, float *recgrad,
-                             float *colour_partials, hipStream_t st);
+                             float *colour_partials, const unsigned long long *cmask,
+                             hipStream_t st);
+// Contributor masks (8x8 tiles): for tile t with list start s, word w of pixel (lane) l is
+// cmask[(s / 64 + t + w) * 64 + l], bit b set iff list position 64 w + b was composited;
+// the ranges of different tiles are disjoint, so (pairs / 64 + tiles + 1) * 64 words suffice.
+size_t cmask_words(int64_t pair_cap, int32_t tiles);
 hipError_t launch_colour_reduce(const float *partials, int32_t nv, const ViewDesc *views,
                                 float *d_colC, float *d_colc, float *d_amb, hipStream_t st);
 int project_bwd_blocks(int64_t n);
