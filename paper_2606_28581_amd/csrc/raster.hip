@@ -89,9 +89,12 @@ __global__ __launch_bounds__(256) void k_project(
     float4 *__restrict__ rec, short4 *__restrict__ tiles, uint32_t *__restrict__ counts,
     const uint32_t *__restrict__ tmask)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the block's 256 records are staged in LDS and written back as one contiguous run
+    __shared__ float4 srec[256 * kRecVec4];
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+    const bool valid = r0 + threadIdx.x < n;
+    const int64_t r = valid ? r0 + threadIdx.x : n - 1;   // lanes past the end repeat the last
     const int v = blockIdx.y;
-    if (r >= n) return;
     const ViewDesc vd = views[v];
     double B[2][3], b[2];
     if (sun) {
@@ -183,14 +186,16 @@ __global__ __launch_bounds__(256) void k_project(
     } else {
         tl.x = 0; tl.y = -1; tl.z = 0; tl.w = -1;
     }
-    tiles[slot] = tl;
-    counts[slot] = cnt;
+    if (valid) {
+        tiles[slot] = tl;
+        counts[slot] = cnt;
+    }
     // record
     const float chx = (float)c[0], chy = (float)c[1];
     const uint32_t boxx = ((uint32_t)(uint16_t)ilo) | ((uint32_t)(uint16_t)ihi << 16);
     const uint32_t boxy = ((uint32_t)(uint16_t)jlo) | ((uint32_t)(uint16_t)jhi << 16);
     const float inf = __builtin_inff();
-    float4 *R = rec + 6 * slot;
+    float4 *R = srec + kRecVec4 * threadIdx.x;
     R[0] = make_float4(__uint_as_float(boxx), __uint_as_float(boxy), chx, chy);
     R[1] = make_float4((float)(c[0] - (double)chx), (float)(c[1] - (double)chy),
                        deg ? inf : 0.f, filt ? 0.f : inf);
@@ -201,6 +206,10 @@ __global__ __launch_bounds__(256) void k_project(
     R[4] = make_float4(pd.x, pd.y, pd.z, vv);
     const double s = nsign / mn;
     R[5] = make_float4((float)(s * m[0]), (float)(s * m[1]), (float)(s * m[2]), (float)nsign);
+    __syncthreads();
+    const int64_t nrec = min((int64_t)blockDim.x, n - r0);
+    float4 *dst = rec + ((size_t)v * (size_t)n + (size_t)r0) * kRecVec4;
+    for (int i = threadIdx.x; i < nrec * kRecVec4; i += blockDim.x) dst[i] = srec[i];
 }
 
 hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order, int32_t nv,
