@@ -54,7 +54,7 @@ struct Layout {
     size_t rec_main, tiles_main, counts_main, offs_main, scanparts;
     size_t pk_a, pv_a, pk_b, pv_b, ranges_main, recgrad, colour_parts, dF_parts;
     size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
-    size_t sun_depth, bounds, radix_temp, tmask_sun, cmask, cmask_bytes;
+    size_t sun_depth, bounds, radix_temp, tmask_sun, cmask, cmask_bytes, stat_main, stat_sun;
     size_t total;
 };
 
@@ -174,6 +174,8 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.views_sun = take(nv * sizeof(ViewDesc));
     L.suncam = take(nv * sizeof(SunCam));
     L.counters = take(16 * sizeof(unsigned long long));
+    L.stat_main = take((size_t)kStatSlots * kStatStride * sizeof(unsigned long long));
+    L.stat_sun = take((size_t)kStatSlots * kStatStride * sizeof(unsigned long long));
     L.flags = take(16 * sizeof(uint32_t));
     L.mk_a = take(n * 4); L.mk_b = take(n * 4); L.mv_a = take(n * 4); L.mv_b = take(n * 4);
     L.sorted_main = take(n * 16 * 4);
@@ -574,8 +576,8 @@ ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const f
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     p->fwd_valid = false;
     SS_HIP(fill_u32(p->at<uint32_t>(p->L.flags), 0u, 1, st));
-    unsigned long long *counters = p->at<unsigned long long>(p->L.counters);
-    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 2), 0u, 4, st));
+    unsigned long long *stat = p->at<unsigned long long>(p->L.stat_main);
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
     uint32_t *order;
     float *sorted;
     if ((e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
@@ -588,7 +590,7 @@ ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const f
                                  p->at<uint32_t>(p->L.ranges_main), p->lists_main,
                                  p->at<float>(p->L.rec_main), p->n, rc, v->colC, v->colc,
                                  v->ambient, nullptr, image, albedo_out, vis_out, depth, normal,
-                                 T_final, last, counters + 2, cmask_ptr(p), st));
+                                 T_final, last, stat, cmask_ptr(p), st));
     }
     p->order_main = order;
     p->fwd_valid = true;
@@ -654,8 +656,8 @@ ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, fl
     const Layout &L = p->L;
     p->sun_valid = false;
     SS_HIP(fill_u32(p->at<uint32_t>(L.flags) + 1, 0u, 1, st));
-    unsigned long long *counters = p->at<unsigned long long>(L.counters);
-    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 4), 0u, 4, st));
+    unsigned long long *stat = p->at<unsigned long long>(L.stat_sun);
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
     uint32_t *order;
     float *sorted;
     if ((e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
@@ -674,7 +676,7 @@ ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, fl
                                  p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
                                  p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
                                  nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
-                                 nullptr, nullptr, nullptr, counters + 4, nullptr, st));
+                                 nullptr, nullptr, nullptr, stat, nullptr, st));
     }
     {
         StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);
@@ -1039,7 +1041,9 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
     p->sun_valid = false;
     unsigned long long *counters = p->at<unsigned long long>(L.counters);
     SS_HIP(fill_u32(p->at<uint32_t>(L.flags) + 1, 0u, 1, st));
-    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 4), 0u, 6, st));
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(counters + 6), 0u, 2, st));
+    unsigned long long *stat = p->at<unsigned long long>(L.stat_sun);
+    SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
     {
         StageScope scope(p, SS_STAGE_MLP, st);
         SS_HIP(launch_mlp_prep(w, mlp->at<uint16_t>(mlp->o_wb), mlp->at<float>(mlp->o_wf), st));
@@ -1073,7 +1077,7 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
                                  p->at<ViewDesc>(L.views_sun), p->at<uint32_t>(L.ranges_sun),
                                  p->lists_sun, p->at<float>(L.rec_sun), p->n, rc, nullptr, nullptr,
                                  nullptr, p->at<SunCam>(L.suncam), nullptr, nullptr, nullptr, D,
-                                 nullptr, nullptr, nullptr, counters + 4, nullptr, st));
+                                 nullptr, nullptr, nullptr, stat, nullptr, st));
     }
     {
         StageScope scope(p, SS_STAGE_SHADOW_QUERY, st);
@@ -1131,8 +1135,18 @@ ss_status ss_plan_stats(ss_plan *p, int64_t *out, ss_stream stream)
     if (!p || !p->ws || !out) return fail(SS_ERR_INVALID_ARG, "plan/workspace/out missing");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     unsigned long long c[7];
+    std::vector<unsigned long long> sm((size_t)kStatSlots * kStatStride), ss((size_t)kStatSlots * kStatStride);
     SS_HIP(hipMemcpyAsync(c, p->at<void>(p->L.counters), sizeof c, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(sm.data(), p->at<void>(p->L.stat_main), sm.size() * 8, hipMemcpyDeviceToHost, st));
+    SS_HIP(hipMemcpyAsync(ss.data(), p->at<void>(p->L.stat_sun), ss.size() * 8, hipMemcpyDeviceToHost, st));
     SS_HIP(hipStreamSynchronize(st));
+    // pairs main, contributing main, evaluated main, pairs sun, contributing sun, evaluated
+    // sun, surrogate fallback points
+    for (int k = 2; k < 6; ++k) c[k] = 0;
+    for (int q = 0; q < kStatSlots; ++q) {
+        c[2] += sm[(size_t)q * kStatStride]; c[3] += sm[(size_t)q * kStatStride + 1];
+        c[4] += ss[(size_t)q * kStatStride]; c[5] += ss[(size_t)q * kStatStride + 1];
+    }
     const int map[7] = {0, 2, 3, 1, 4, 5, 6};
     for (int k = 0; k < 7; ++k) out[k] = (int64_t)c[map[k]];
     return SS_OK;

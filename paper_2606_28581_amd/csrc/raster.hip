@@ -496,15 +496,16 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     if (CM && cmask && wcur >= 0) cmask[(wbase + wcur) * 64 + tid] = wacc;
 #undef SS_FETCH_FWD
     {
-        // work counters: one 64-bit atomic per wave and counter
+        // work counters: one 64-bit atomic per wave and counter, into the tile's slot
         unsigned long long c = (unsigned long long)ncontrib, e = (unsigned long long)neval;
         for (int d = 32; d > 0; d >>= 1) {
             c += __shfl_xor(c, d, 64);
             e += __shfl_xor(e, d, 64);
         }
         if (lane == 0) {
-            atomicAdd(stats, c);
-            atomicAdd(stats + 1, e);
+            unsigned long long *slot = stats + (size_t)(tile % kStatSlots) * kStatStride;
+            atomicAdd(slot, c);
+            atomicAdd(slot + 1, e);
         }
     }
     if (!inside) return;

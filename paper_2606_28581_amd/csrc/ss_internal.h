@@ -29,6 +29,11 @@ constexpr int kWave = 64;
 //   v      : sun visibility composited into the V channel (1 when none is given)
 //   nsign  : +-1, normal orientation (n = nsign * m / |m|, m = t_u x t_v)
 // The depth-only (sun-view) raster reads only vec4 0..3.
+// Raster work counters (contributing, evaluated pairs): every wave adds to the slot of its
+// tile modulo kStatSlots, each slot on its own 128-byte line, so the adds of 10^6 waves
+// do not queue on one address; readers sum the slots.
+constexpr int kStatSlots = 256;
+constexpr int kStatStride = 16;   // 64-bit words per slot
 constexpr int kRecFloats = 24;
 constexpr int kRecVec4 = 6;
 
