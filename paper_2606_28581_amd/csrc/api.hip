@@ -201,7 +201,7 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.ranges_sun = take((size_t)p->tiles_sun_max * 8);
     L.sun_depth = take(nv * S * S * 4);
     L.bounds = take((size_t)bounds_blocks(p->n) * 6 * 8);
-    L.radix_temp = take(radix_temp_bytes(std::max<int64_t>(p->n, std::max(cm, cs))));
+    L.radix_temp = take(radix_temp_bytes(std::max<int64_t>(p->n, std::max(cm, cs)), p->nv));
     L.tmask_sun = take((size_t)p->tiles_sun_max * 4);
     // forward -> backward contributor masks of 8x8 tiles (other sizes use the box test)
     L.cmask_bytes = p->st.tile_size == 8 ? cmask_words(cm, p->tiles_main_max) * 8 : 0;
@@ -317,14 +317,19 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
     uint32_t *kb = p->at<uint32_t>(sun ? L.qk_b : L.pk_b), *vb = p->at<uint32_t>(sun ? L.qv_b : L.pv_b);
     SS_HIP(launch_emit(order, p->n, p->nv, views, tiles, counts, offs, (uint64_t)cap, ka, va, tmask,
                        st));
+    // pairs arrive grouped by view (the count scan is view-major) and in depth-rank order
+    // inside a view, so a stable sort on the tile id inside each view's run is the whole
+    // bucketing; its last pass also writes each tile's list range
     const int32_t ntiles = sun ? p->tiles_sun : p->tiles_main;
+    int64_t view_tiles = 1;
+    for (const ViewDesc &d : sun ? p->vsun : p->vmain)
+        view_tiles = std::max<int64_t>(view_tiles, (int64_t)d.tiles_x * d.tiles_y);
+    SortSegments seg{offs, p->n, p->nv, views,
+                     p->at<uint32_t>(sun ? L.ranges_sun : L.ranges_main), ntiles};
     bool in_b = false;
-    SS_HIP(radix_sort_pairs(ka, va, kb, vb, cap, counters + (sun ? 1 : 0), 0, bits_for(ntiles),
-                            p->at<void>(L.radix_temp), &in_b, st));
-    uint32_t *keys = in_b ? kb : ka;
+    SS_HIP(radix_sort_pairs(ka, va, kb, vb, cap, counters + (sun ? 1 : 0), 0, bits_for(view_tiles),
+                            p->at<void>(L.radix_temp), &in_b, st, &seg));
     uint32_t *lists = in_b ? vb : va;
-    SS_HIP(launch_ranges(keys, counters + (sun ? 1 : 0), cap, ntiles,
-                         p->at<uint32_t>(sun ? L.ranges_sun : L.ranges_main), st));
     if (sun) p->lists_sun = lists; else p->lists_main = lists;
     return SS_OK;
 }

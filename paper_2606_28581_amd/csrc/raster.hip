@@ -267,30 +267,6 @@ hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- tile ranges
-__global__ void k_ranges(const uint32_t *__restrict__ keys, const unsigned long long *n_dev,
-                         int64_t cap, int64_t n_tiles, uint32_t *__restrict__ ranges)
-{
-    unsigned long long nn = *n_dev;
-    const int64_t n = nn < (unsigned long long)cap ? (int64_t)nn : cap;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t k = keys[i];
-    if ((int64_t)k >= n_tiles) return;
-    if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)i;
-    if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
-}
-
-hipError_t launch_ranges(const uint32_t *keys, const unsigned long long *n_dev, int64_t cap,
-                         int64_t n_tiles, uint32_t *ranges, hipStream_t st)
-{
-    hipError_t e = fill_u32(ranges, 0u, 2 * n_tiles, st);
-    if (e != hipSuccess || cap <= 0) return e;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, st, keys,
-                       n_dev, cap, n_tiles, ranges);
-    return hipGetLastError();
-}
-
 // ------------------------------------------------------------ per-pair evaluation
 // The same FP32 sequence runs in the forward and the backward so both take the same
 // discrete decisions (skip, stop, branch).

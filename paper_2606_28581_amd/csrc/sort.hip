@@ -175,30 +175,153 @@ hipError_t scan_pair_counts(const uint32_t *counts, int64_t n, int32_t nv,
 }
 
 // ------------------------------------------------------------------ radix sort
+// Blocks never straddle a segment: block b of segment v covers items
+// [start_v + j * kSortTile, ...) with j = b - blk0_v, and its digits are taken from
+// key - base_v.  The histogram of block b sits at blk0_v * 256 + digit * nblk_v + j, so
+// one exclusive scan over all blocks' histograms gives every (segment, digit, block) its
+// output position inside its own segment.  Blocks past the last live one write zeros at
+// b * 256 + digit, after every live block's entries.
+struct SegDesc {
+    uint32_t start, end, blk0, base;
+};
+
+struct BlockRange {
+    int64_t lo, hi;
+    uint32_t base;
+    int64_t hidx0;      // histogram index of digit 0
+    int64_t hstride;    // histogram index step per digit
+    bool live;
+};
+
+__device__ __forceinline__ BlockRange block_range(const SegDesc *segs, int nseg,
+                                                  const unsigned long long *n_dev, int64_t cap,
+                                                  int64_t n_host, int64_t b)
+{
+    BlockRange r;
+    if (!segs) {
+        const int64_t n = live_count(n_dev, cap, n_host);
+        const int64_t nb = (n + kSortTile - 1) / kSortTile;
+        r.lo = b * kSortTile;
+        r.hi = min(n, r.lo + kSortTile);
+        r.base = 0;
+        r.live = b < nb;
+        r.hidx0 = r.live ? b : b * 256;
+        r.hstride = r.live ? nb : 1;
+        return r;
+    }
+    const int64_t total = segs[nseg].blk0;
+    r.live = b < total;
+    if (!r.live) {
+        r.lo = r.hi = 0;
+        r.base = 0;
+        r.hidx0 = b * 256;
+        r.hstride = 1;
+        return r;
+    }
+    // last segment whose first block is <= b (segments without blocks share blk0 with
+    // the next one and are skipped by taking the last)
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)segs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const SegDesc sd = segs[lo];
+    const int64_t j = b - sd.blk0;
+    const int64_t nblk = (int64_t)segs[lo + 1].blk0 - sd.blk0;
+    r.lo = (int64_t)sd.start + j * kSortTile;
+    r.hi = min((int64_t)sd.end, r.lo + kSortTile);
+    r.base = sd.base;
+    r.hidx0 = (int64_t)sd.blk0 * 256 + j;
+    r.hstride = nblk;
+    return r;
+}
+
+// Lanes of the wave whose `valid` item has the same digit as this lane (over the low
+// `nbits` bits of d).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid, int nbits)
+{
+    uint64_t m = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        m &= bit ? bb : ~bb;
+    }
+    return m;
+}
+
+// One block: segment table from view-major pair offsets.  Segment v holds the items
+// [offs[v * stride], offs[(v + 1) * stride]) clamped to the live count; its keys are
+// based at views[v].tile_off.
+constexpr int kSegThreads = 1024;
+
+__global__ __launch_bounds__(kSegThreads) void k_seg_table(
+    const uint32_t *offs, int64_t stride, int32_t nseg, const ViewDesc *views,
+    const unsigned long long *n_dev, int64_t cap, SegDesc *segs)
+{
+    __shared__ uint32_t lds_w[kSegThreads / kWave];
+    __shared__ uint32_t carry;
+    const int64_t n = live_count(n_dev, cap, cap);
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t v0 = 0; v0 <= nseg; v0 += kSegThreads) {
+        const int32_t v = v0 + (int32_t)threadIdx.x;
+        uint32_t st = 0, en = 0, nblk = 0;
+        if (v <= nseg) {
+            st = (uint32_t)min((int64_t)offs[(int64_t)v * stride], n);
+            en = v < nseg ? (uint32_t)min((int64_t)offs[(int64_t)(v + 1) * stride], n) : st;
+            en = max(en, st);
+            nblk = v < nseg ? (en - st + kSortTile - 1) / kSortTile : 0u;
+        }
+        const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+        uint32_t inc = nblk;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += y;
+        }
+        if (lane == kWave - 1) lds_w[w] = inc;
+        __syncthreads();
+        uint32_t wbase = 0, tot = 0;
+        for (int k = 0; k < kSegThreads / kWave; ++k) {
+            if (k < w) wbase += lds_w[k];
+            tot += lds_w[k];
+        }
+        if (v <= nseg)
+            segs[v] = SegDesc{st, en, carry + wbase + inc - nblk,
+                              v < nseg ? (uint32_t)views[v].tile_off : 0u};
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
-    const uint32_t *keys, const unsigned long long *n_dev, int64_t cap, int64_t n_host,
-    int shift, uint32_t *hist, int nblocks)
+    const uint32_t *keys, const SegDesc *segs, int nseg, const unsigned long long *n_dev,
+    int64_t cap, int64_t n_host, int shift, int nbits, uint32_t *hist)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t n = live_count(n_dev, cap, n_host);
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    if (base < n) {
+    const BlockRange br = block_range(segs, nseg, n_dev, cap, n_host, blockIdx.x);
+    if (br.live) {
         const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-        const int64_t wbase = base + (int64_t)w * (kSortItems * kWave);
-#pragma unroll 4
+        const int64_t wbase = br.lo + (int64_t)w * (kSortItems * kWave);
+        const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
         for (int it = 0; it < kSortItems; ++it) {
-            int64_t i = wbase + it * kWave + lane;
-            if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+            const int64_t i = wbase + it * kWave + lane;
+            const bool valid = i < br.hi;
+            if (__ballot(valid) == 0) break;
+            const uint32_t d = valid ? ((keys[i] - br.base) >> shift) & 255u : 0u;
+            // one LDS add per group of lanes with the same digit (its lowest lane)
+            const uint64_t m = digit_peers(d, valid, nbits);
+            if (valid && (m & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(m));
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[br.hidx0 + (int64_t)threadIdx.x * br.hstride] = h[threadIdx.x];
 }
 
-// Exclusive scan over hist[256 * nblocks] (digit-major), single pass per block chunk
-// using the same three-kernel scheme as the pair counts but on a 32-bit total.
+// Exclusive scan over the histograms, single pass per block chunk using the same
+// three-kernel scheme as the pair counts but on a 32-bit total.
 __global__ void k_hist_scan_reduce(uint32_t *hist, int64_t len, uint32_t *partials)
 {
     __shared__ uint32_t lds[kSortWaves];
@@ -242,39 +365,36 @@ __global__ __launch_bounds__(kScanPartialsThreads) void k_hist_scan_partials(uin
     }
 }
 
+// With `ranges` (the last pass), every block also reports, per key, the first and last
+// output position of its run: ranges[2k] = min over blocks, ranges[2k + 1] = max + 1.
+// A block holds its items in LDS sorted by the whole key (stable on the top digit of
+// items that the lower passes left sorted), so equal keys are adjacent there.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
-    const uint32_t *offs, const unsigned long long *n_dev, int64_t cap, int64_t n_host,
-    int shift, int nblocks)
+    const uint32_t *offs, const SegDesc *segs, int nseg, const unsigned long long *n_dev,
+    int64_t cap, int64_t n_host, int shift, int nbits, uint32_t *ranges, int64_t nkeys)
 {
     __shared__ uint32_t wcnt[kSortWaves][256];
     __shared__ uint32_t dbase[256];          // block-local start of each digit's run
     __shared__ uint32_t gshift[256];         // global start minus local start, per digit
     __shared__ uint32_t lds_w[kSortWaves];
     __shared__ uint32_t skey[kSortTile], sval[kSortTile];
-    const int64_t n = live_count(n_dev, cap, n_host);
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
-    if (base >= n) return;   // uniform over the block
+    const BlockRange br = block_range(segs, nseg, n_dev, cap, n_host, blockIdx.x);
+    if (!br.live) return;   // uniform over the block
     for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int64_t wbase = base + (int64_t)w * (kSortItems * kWave);
+    const int64_t wbase = br.lo + (int64_t)w * (kSortItems * kWave);
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t i = wbase + it * kWave + lane;
-        const bool valid = i < n;
+        const bool valid = i < br.hi;
         key[it] = valid ? kin[i] : 0u;
         val[it] = valid ? vin[i] : 0u;
-        const uint32_t d = (key[it] >> shift) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
+        const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
+        const uint64_t m = digit_peers(d, valid, nbits);
         const uint32_t before = __popcll(m & lt_mask);
         const uint32_t cur = wcnt[w][d];
         rank[it] = cur + before;
@@ -296,14 +416,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         uint32_t tot;
         const uint32_t excl = block_exclusive_scan(run, lds_w, &tot);
         dbase[d] = excl;
-        gshift[d] = offs[(int64_t)d * nblocks + blockIdx.x] - excl;
+        gshift[d] = offs[br.hidx0 + (int64_t)d * br.hstride] - excl;
     }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t i = wbase + it * kWave + lane;
-        if (i < n) {
-            const uint32_t d = (key[it] >> shift) & 255u;
+        if (i < br.hi) {
+            const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
             const uint32_t lp = dbase[d] + wcnt[w][d] + rank[it];
             if (lp < (uint32_t)kSortTile) {   // always true when the counts agree
                 skey[lp] = key[it];
@@ -314,44 +434,83 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
     // digit runs are contiguous in LDS and in the output: consecutive threads write
     // consecutive addresses within a run
-    const int nloc = (int)min((int64_t)kSortTile, n - base);
+    const int nloc = (int)(br.hi - br.lo);
+    const int64_t n_out = segs ? (int64_t)segs[nseg].end : live_count(n_dev, cap, n_host);
     for (int i = threadIdx.x; i < nloc; i += kSortThreads) {
         const uint32_t k = skey[i];
-        const uint32_t pos = gshift[(k >> shift) & 255u] + (uint32_t)i;
-        if (pos < n) {   // always true when histogram and scatter agree
+        const uint32_t pos = gshift[((k - br.base) >> shift) & 255u] + (uint32_t)i;
+        if (pos < n_out) {   // always true when histogram and scatter agree
             kout[pos] = k;
             vout[pos] = sval[i];
+            if (ranges && (int64_t)k < nkeys) {
+                if (i == 0 || skey[i - 1] != k) atomicMin(&ranges[2 * (int64_t)k], pos);
+                if (i == nloc - 1 || skey[i + 1] != k) atomicMax(&ranges[2 * (int64_t)k + 1], pos + 1);
+            }
         }
     }
 }
 
+__global__ void k_ranges_init(uint32_t *ranges, int64_t nkeys)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nkeys) reinterpret_cast<uint2 *>(ranges)[k] = make_uint2(0xFFFFFFFFu, 0u);
+}
+
+__global__ void k_ranges_finish(uint32_t *ranges, int64_t nkeys)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nkeys) return;
+    uint2 r = reinterpret_cast<uint2 *>(ranges)[k];
+    if (r.x == 0xFFFFFFFFu) reinterpret_cast<uint2 *>(ranges)[k] = make_uint2(0u, 0u);
+}
+
 static int64_t sort_blocks(int64_t items) { return (items + kSortTile - 1) / kSortTile; }
 
-size_t radix_temp_bytes(int64_t max_items)
+size_t radix_temp_bytes(int64_t max_items, int32_t max_segs)
 {
-    int64_t nb = sort_blocks(max_items > 0 ? max_items : 1);
-    int64_t hist = 256 * nb;
-    int64_t parts = (hist + kSortTile - 1) / kSortTile + 1;
-    return (size_t)(hist + parts) * sizeof(uint32_t) + 256;
+    const int64_t nb = sort_blocks(max_items > 0 ? max_items : 1) + max_segs;
+    const int64_t hist = 256 * nb;
+    const int64_t parts = (hist + kSortTile - 1) / kSortTile + 1;
+    return (size_t)(hist + parts) * sizeof(uint32_t) + 256 +
+           (size_t)(max_segs + 1) * sizeof(SegDesc) + 256;
 }
 
 hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b,
                             uint32_t *vals_b, int64_t cap, const unsigned long long *n_dev,
                             int64_t n_host, int bits, void *temp, bool *result_in_b,
-                            hipStream_t st)
+                            hipStream_t st, const SortSegments *seg)
 {
     *result_in_b = false;
     const int64_t items = n_dev ? cap : n_host;
-    const int64_t nb = sort_blocks(items);
-    if (nb == 0 || bits <= 0) return hipSuccess;
+    const int32_t nseg = seg ? seg->nseg : 0;
+    const int64_t nb = sort_blocks(items) + nseg;
+    if (sort_blocks(items) == 0) {
+        if (seg && seg->ranges && seg->nkeys > 0)
+            return fill_u32(seg->ranges, 0u, 2 * seg->nkeys, st);
+        return hipSuccess;
+    }
     uint32_t *hist = reinterpret_cast<uint32_t *>(temp);
     const int64_t hlen = 256 * nb;
-    uint32_t *parts = hist + hlen;
     const int64_t nparts = (hlen + kSortTile - 1) / kSortTile;
+    uint32_t *parts = hist + hlen;
+    SegDesc *segs = nullptr;
+    if (seg) {
+        const size_t off = ((size_t)(hlen + nparts + 1) * sizeof(uint32_t) + 255) & ~size_t(255);
+        segs = reinterpret_cast<SegDesc *>(static_cast<char *>(temp) + off);
+        hipLaunchKernelGGL(k_seg_table, dim3(1), dim3(kSegThreads), 0, st, seg->offs, seg->stride,
+                           nseg, seg->views, n_dev, cap, segs);
+        if (seg->ranges && seg->nkeys > 0)
+            hipLaunchKernelGGL(k_ranges_init, dim3((unsigned)((seg->nkeys + 255) / 256)), dim3(256),
+                               0, st, seg->ranges, seg->nkeys);
+    }
+    uint32_t *ranges = seg && seg->nkeys > 0 ? seg->ranges : nullptr;
+    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;   // one pass at least: ranges come from it
     uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
-    for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
-                           n_dev, cap, n_host, shift, hist, (int)nb);
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const int nbits = std::max(1, std::min(8, bits - shift));
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, segs,
+                           nseg, n_dev, cap, n_host, shift, nbits, hist);
         hipLaunchKernelGGL(k_hist_scan_reduce, dim3((unsigned)nparts), dim3(kSortThreads), 0,
                            st, hist, hlen, parts);
         hipLaunchKernelGGL(k_hist_scan_partials, dim3(1), dim3(kScanPartialsThreads), 0, st, parts,
@@ -359,11 +518,15 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nparts), dim3(kSortThreads), 0, st,
                            hist, hlen, parts, hist);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
-                           vi, ko, vo, hist, n_dev, cap, n_host, shift, (int)nb);
+                           vi, ko, vo, hist, segs, nseg, n_dev, cap, n_host, shift, nbits,
+                           p == passes - 1 ? ranges : nullptr, seg ? seg->nkeys : 0);
         std::swap(ki, ko);
         std::swap(vi, vo);
         *result_in_b = !*result_in_b;
     }
+    if (ranges)
+        hipLaunchKernelGGL(k_ranges_finish, dim3((unsigned)((seg->nkeys + 255) / 256)), dim3(256),
+                           0, st, ranges, seg->nkeys);
     return hipGetLastError();
 }
 

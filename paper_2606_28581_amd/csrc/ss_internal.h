@@ -75,7 +75,8 @@ struct SurfelPtrs {
 
 // ------------------------------------------------------------------- launchers
 // sort.hip
-size_t radix_temp_bytes(int64_t max_items);
+// Temp bytes of radix_sort_pairs for up to max_items items in up to max_segs segments.
+size_t radix_temp_bytes(int64_t max_items, int32_t max_segs);
 hipError_t fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t st);
 hipError_t fill_f32(float *p, float value, int64_t count, hipStream_t st);
 // Exclusive scan of per-(view, rank) tile counts (contiguous, depth-rank order):
@@ -86,13 +87,27 @@ hipError_t scan_pair_counts(const uint32_t *counts, int64_t n,
                             unsigned long long *counters, int which, uint32_t *flags,
                             uint64_t cap, hipStream_t st);
 size_t scan_temp_elems(int64_t len);
-// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of key.
-// Item count is n_dev ? min(*n_dev, cap) : n_host.  Returns (via *result_in_b) whether
-// the sorted data ended in the b buffers.
+// Items that arrive grouped in segments, each sorted on its own keys minus a base:
+// segment v holds items [offs[v * stride], offs[(v + 1) * stride]) (clamped to the live
+// count) with keys in [views[v].tile_off, views[v].tile_off + 2^bits).  The result equals
+// a stable sort of the whole array on the key.  With `ranges` (nkeys entries of
+// (begin, end), interleaved), the sort also writes each key's output run; keys with no
+// item get (0, 0).
+struct SortSegments {
+    const uint32_t *offs;
+    int64_t stride;
+    int32_t nseg;
+    const ViewDesc *views;
+    uint32_t *ranges;
+    int64_t nkeys;
+};
+// Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of key
+// (of key minus its segment base with `seg`).  Item count is n_dev ? min(*n_dev, cap) :
+// n_host.  Returns (via *result_in_b) whether the sorted data ended in the b buffers.
 hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b,
                             uint32_t *vals_b, int64_t cap, const unsigned long long *n_dev,
                             int64_t n_host, int bits, void *temp, bool *result_in_b,
-                            hipStream_t st);
+                            hipStream_t st, const SortSegments *seg = nullptr);
 
 // raster.hip
 hipError_t launch_depth_keys(const float *mean, int64_t n, float bz, uint32_t *keys,
@@ -108,8 +123,6 @@ hipError_t launch_emit(const uint32_t *order, int64_t n, int32_t nv, const ViewD
                        const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
                        uint64_t cap, uint32_t *keys, uint32_t *vals, const uint32_t *tmask,
                        hipStream_t st);
-hipError_t launch_ranges(const uint32_t *keys, const unsigned long long *n_dev, int64_t cap,
-                         int64_t n_tiles, uint32_t *ranges, hipStream_t st);
 hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
                              int32_t nv, const ViewDesc *views, const uint32_t *ranges,
                              const uint32_t *lists, const float *rec, int64_t n,
