@@ -227,33 +227,61 @@ hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order,
 }
 
 // ------------------------------------------------------------------------ emit
-// One thread per (rank, view): write one (global tile id, rank) pair per overlapped
-// tile at the scanned offset.  Pairs beyond the bound capacity are dropped (the scan
-// already raised the overflow flag).
-__global__ void k_emit(int64_t n, const ViewDesc *__restrict__ views,
-                       const short4 *__restrict__ tiles, const uint32_t *__restrict__ counts,
-                       const uint32_t *__restrict__ offsets, uint64_t cap,
-                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                       const uint32_t *__restrict__ tmask)
+// One thread per (rank, view): one (global tile id, rank) pair per overlapped tile at
+// the scanned offset.  A block's 256 ranks own one contiguous run of the output; runs
+// of up to kEmitStage pairs are assembled in LDS and written out coalesced, longer ones
+// go straight to memory.  Pairs beyond the bound capacity are dropped (the scan already
+// raised the overflow flag).
+constexpr int kEmitThreads = 256;
+constexpr int kEmitStage = 1024;
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit(
+    int64_t n, const ViewDesc *__restrict__ views, const short4 *__restrict__ tiles,
+    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, uint64_t cap,
+    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, const uint32_t *__restrict__ tmask)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t sk[kEmitStage], sv[kEmitStage];
     const int v = blockIdx.y;
-    if (r >= n) return;
-    const int64_t slot = (int64_t)v * n + r;
-    if (counts[slot] == 0) return;
-    const short4 t = tiles[slot];
-    const ViewDesc vd = views[v];
-    uint64_t pos = offsets[slot];
-    for (int ty = t.z; ty <= t.w; ++ty)
-        for (int tx = t.x; tx <= t.y; ++tx) {
-            const uint32_t key = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
-            if (tmask && tmask[key] == 0u) continue;
-            if (pos < cap) {
-                keys[pos] = key;
-                vals[pos] = (uint32_t)r;
-            }
-            ++pos;
+    const int64_t r0 = (int64_t)blockIdx.x * kEmitThreads;
+    const int64_t r = r0 + threadIdx.x;
+    const int64_t rend = min(n, r0 + kEmitThreads);
+    const uint64_t b_lo = offsets[(int64_t)v * n + r0];
+    const uint64_t b_hi = max(b_lo, (uint64_t)offsets[(int64_t)v * n + rend]);
+    const bool staged = b_hi - b_lo <= (uint64_t)kEmitStage;   // uniform over the block
+    if (r < n) {
+        const int64_t slot = (int64_t)v * n + r;
+        if (counts[slot] != 0) {
+            const short4 t = tiles[slot];
+            const ViewDesc vd = views[v];
+            uint64_t pos = offsets[slot];
+            for (int ty = t.z; ty <= t.w; ++ty)
+                for (int tx = t.x; tx <= t.y; ++tx) {
+                    const uint32_t key = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
+                    if (tmask && tmask[key] == 0u) continue;
+                    if (staged) {
+                        const uint64_t l = pos - b_lo;
+                        if (l < (uint64_t)kEmitStage) {
+                            sk[l] = key;
+                            sv[l] = (uint32_t)r;
+                        }
+                    } else if (pos < cap) {
+                        keys[pos] = key;
+                        vals[pos] = (uint32_t)r;
+                    }
+                    ++pos;
+                }
         }
+    }
+    if (!staged) return;
+    __syncthreads();
+    const int cnt = (int)(b_hi - b_lo);
+    for (int i = threadIdx.x; i < cnt; i += kEmitThreads) {
+        const uint64_t pos = b_lo + (uint64_t)i;
+        if (pos < cap) {
+            keys[pos] = sk[i];
+            vals[pos] = sv[i];
+        }
+    }
 }
 
 hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *views,
@@ -262,8 +290,9 @@ hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *
                        hipStream_t st)
 {
     if (n <= 0 || cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0, st,
-                       n, views, tiles, counts, offsets, cap, keys, vals, tmask);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + kEmitThreads - 1) / kEmitThreads), (unsigned)nv),
+                       dim3(kEmitThreads), 0, st, n, views, tiles, counts, offsets, cap, keys, vals,
+                       tmask);
     return hipGetLastError();
 }
 

@@ -77,14 +77,48 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *l
 }
 
 // ------------------------------------------------------------- pair-count scan
+// Each thread owns kSortItems consecutive entries; full groups are moved as uint4 (the
+// arrays start 256-byte aligned and a group starts at a multiple of 16 entries).
+__device__ __forceinline__ void load_items(const uint32_t *in, int64_t base, int64_t len,
+                                           uint32_t (&v)[kSortItems])
+{
+    if (base + kSortItems <= len) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(in + base);
+#pragma unroll
+        for (int q = 0; q < kSortItems / 4; ++q) {
+            const uint4 x = p[q];
+            v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) v[i] = base + i < len ? in[base + i] : 0u;
+    }
+}
+
+__device__ __forceinline__ void store_items(uint32_t *out, int64_t base, int64_t len,
+                                            const uint32_t (&v)[kSortItems])
+{
+    if (base + kSortItems <= len) {
+        uint4 *p = reinterpret_cast<uint4 *>(out + base);
+#pragma unroll
+        for (int q = 0; q < kSortItems / 4; ++q)
+            p[q] = make_uint4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i)
+            if (base + i < len) out[base + i] = v[i];
+    }
+}
+
 __global__ void k_scan_reduce(const uint32_t *in, int64_t len, uint32_t *partials)
 {
     __shared__ uint32_t lds[kSortWaves];
     int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t v[kSortItems];
+    load_items(in, base, len, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i)
-        if (base + i < len) s += in[base + i];
+    for (int i = 0; i < kSortItems; ++i) s += v[i];
     uint32_t tot;
     block_exclusive_scan(s, lds, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -137,19 +171,19 @@ __global__ void k_scan_down(const uint32_t *in, int64_t len, const uint32_t *par
     __shared__ uint32_t lds[kSortWaves];
     int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
     uint32_t v[kSortItems];
+    load_items(in, base, len, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-        v[i] = base + i < len ? in[base + i] : 0u;
-        s += v[i];
-    }
+    for (int i = 0; i < kSortItems; ++i) s += v[i];
     uint32_t tot;
     uint32_t run = block_exclusive_scan(s, lds, &tot) + partials[blockIdx.x];
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
-        if (base + i < len) out[base + i] = run;
-        run += v[i];
+        const uint32_t x = v[i];
+        v[i] = run;
+        run += x;
     }
+    store_items(out, base, len, v);
 }
 
 size_t scan_temp_elems(int64_t len)
@@ -326,10 +360,11 @@ __global__ void k_hist_scan_reduce(uint32_t *hist, int64_t len, uint32_t *partia
 {
     __shared__ uint32_t lds[kSortWaves];
     int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t v[kSortItems];
+    load_items(hist, base, len, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i)
-        if (base + i < len) s += hist[base + i];
+    for (int i = 0; i < kSortItems; ++i) s += v[i];
     uint32_t tot;
     block_exclusive_scan(s, lds, &tot);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -440,7 +475,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const uint32_t k = skey[i];
         const uint32_t pos = gshift[((k - br.base) >> shift) & 255u] + (uint32_t)i;
         if (pos < n_out) {   // always true when histogram and scatter agree
-            kout[pos] = k;
+            if (kout) kout[pos] = k;
             vout[pos] = sval[i];
             if (ranges && (int64_t)k < nkeys) {
                 if (i == 0 || skey[i - 1] != k) atomicMin(&ranges[2 * (int64_t)k], pos);
@@ -517,9 +552,11 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
                            nparts);
         hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nparts), dim3(kSortThreads), 0, st,
                            hist, hlen, parts, hist);
+        // the keys of the last pass are not read again once the ranges are out
+        const bool last = p == passes - 1;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
-                           vi, ko, vo, hist, segs, nseg, n_dev, cap, n_host, shift, nbits,
-                           p == passes - 1 ? ranges : nullptr, seg ? seg->nkeys : 0);
+                           vi, last && ranges ? nullptr : ko, vo, hist, segs, nseg, n_dev, cap,
+                           n_host, shift, nbits, last ? ranges : nullptr, seg ? seg->nkeys : 0);
         std::swap(ki, ko);
         std::swap(vi, vo);
         *result_in_b = !*result_in_b;
