@@ -690,6 +690,100 @@ __device__ __forceinline__ int row_max(int v)
     return v;
 }
 
+// Per-pixel adjoints of Eq. image_formation: the upstream colour gradient through the
+// colour transform and shading gives the gradients of the composited albedo (gA), of
+// the composited visibility (gV), and the pixel's 15 per-view colour-parameter terms
+// (cg[0..8] = dC, cg[9..11] = dc, cg[12..14] = dL_a, cg[15] = 0).
+struct PixelAdjoint {
+    float gA0, gA1, gA2, gV, gD, gN0, gN1, gN2, Tr;
+    int last;
+};
+
+template <bool HAS_VIS>
+__device__ __forceinline__ PixelAdjoint pixel_adjoint(
+    bool inside, int v, int64_t g, int64_t b3, int64_t P, const float *__restrict__ colC,
+    const float *__restrict__ colc, const float *__restrict__ amb, const float *__restrict__ Ain,
+    const float *__restrict__ Vin, const float *__restrict__ Tin,
+    const int32_t *__restrict__ lastin, const float *__restrict__ dI,
+    const float *__restrict__ dD, const float *__restrict__ dN, float (&cg)[16])
+{
+    PixelAdjoint a{0, 0, 0, 0, 0, 0, 0, 0, 1.f, 0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) cg[k] = 0.f;
+    if (!inside) return a;
+    float C[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, cb[3] = {0, 0, 0}, La[3] = {0, 0, 0};
+    if (colC) for (int k = 0; k < 9; ++k) C[k] = colC[9 * v + k];
+    if (colc) for (int k = 0; k < 3; ++k) cb[k] = colc[3 * v + k];
+    if (amb) for (int k = 0; k < 3; ++k) La[k] = amb[3 * v + k];
+    const float A[3] = {Ain[b3], Ain[b3 + P], Ain[b3 + 2 * P]};
+    const float Vp = HAS_VIS ? Vin[g] : 1.f;
+    float gI[3] = {0, 0, 0};
+    if (dI) { gI[0] = dI[b3]; gI[1] = dI[b3 + P]; gI[2] = dI[b3 + 2 * P]; }
+    float gs[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float ca = C[3 * ch] * A[0] + C[3 * ch + 1] * A[1] + C[3 * ch + 2] * A[2] + cb[ch];
+        const float shade = HAS_VIS ? Vp + (1.f - Vp) * La[ch] : 1.f;
+        gs[ch] = gI[ch] * shade;
+        if (HAS_VIS) {
+            a.gV += gI[ch] * ca * (1.f - La[ch]);
+            cg[12 + ch] = gI[ch] * ca * (1.f - Vp);
+        }
+        cg[9 + ch] = gs[ch];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) cg[3 * ch + q] = gs[ch] * A[q];
+    }
+    a.gA0 = C[0] * gs[0] + C[3] * gs[1] + C[6] * gs[2];
+    a.gA1 = C[1] * gs[0] + C[4] * gs[1] + C[7] * gs[2];
+    a.gA2 = C[2] * gs[0] + C[5] * gs[1] + C[8] * gs[2];
+    if (dD) a.gD = dD[g];
+    if (dN) { a.gN0 = dN[b3]; a.gN1 = dN[b3 + P]; a.gN2 = dN[b3 + 2 * P]; }
+    a.Tr = Tin[g];
+    a.last = lastin[g];
+    return a;
+}
+
+// Gradients of one (record, pixel) pair in the back-to-front walk.  Updates the pixel's
+// transmittance Tr and suffix gS when the pair contributes, returns the 16 record
+// gradient values in gr (zero when it does not).
+__device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, float4 r2,
+                                               float4 r3, float4 r4, float4 r5,
+                                               const PixelAdjoint &pa, bool has_vis,
+                                               float two_is2, float alpha_max, float &Tr,
+                                               float &gS, float (&gr)[16])
+{
+    const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
+    const float Tb = Tr * rom;
+    const float w = contrib ? e.alpha * Tb : 0.f;
+    const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+    float gf = pa.gA0 * r4.x + pa.gA1 * r4.y + pa.gA2 * r4.z + pa.gD * z + pa.gN0 * r5.x +
+               pa.gN1 * r5.y + pa.gN2 * r5.z;
+    if (has_vis) gf += pa.gV * r4.w;
+    const float dal = contrib ? Tb * gf - gS * rom : 0.f;
+    gS += w * gf;
+    Tr = contrib ? Tb : Tr;
+    const float dz = w * pa.gD;
+    gr[G_AR] = w * pa.gA0; gr[G_AG] = w * pa.gA1; gr[G_AB] = w * pa.gA2;
+    gr[G_NX] = w * pa.gN0; gr[G_NY] = w * pa.gN1; gr[G_NZ] = w * pa.gN2;
+    gr[G_Z0] = dz;
+    const bool unclamped = e.oG < alpha_max;
+    gr[G_O] = unclamped ? e.G * dal : 0.f;
+    const float dG = unclamped ? r3.x * dal : 0.f;
+    const float drho = -0.5f * e.G * dG;
+    const float du0 = 2.f * e.u0 * drho - r3.z * dz;
+    const float du1 = 2.f * e.u1 * drho - r3.w * dz;
+    gr[G_KU] = e.ub ? -e.u0 * dz : 0.f;
+    gr[G_KV] = e.ub ? -e.u1 * dz : 0.f;
+    gr[G_Q00] = e.ub ? du0 * e.dx : 0.f;
+    gr[G_Q01] = e.ub ? du0 * e.dy : 0.f;
+    gr[G_Q10] = e.ub ? du1 * e.dx : 0.f;
+    gr[G_Q11] = e.ub ? du1 * e.dy : 0.f;
+    const float ddx = e.ub ? r2.x * du0 + r2.z * du1 : two_is2 * e.dx * drho;
+    const float ddy = e.ub ? r2.y * du0 + r2.w * du1 : two_is2 * e.dy * drho;
+    gr[G_CX] = -ddx;
+    gr[G_CY] = -ddy;
+}
+
 // --------------------------------------------------------------- raster backward
 // Back to front over each pixel's contributors [0, last): transmittance before a
 // surfel is recovered as T_i = T_{i+1} / (1 - alpha_i) from T_final, the suffix
@@ -704,7 +798,7 @@ __device__ __forceinline__ int row_max(int v)
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
 template <int TS, bool HAS_VIS>
-__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 && HAS_VIS ? 5 : 4))) void k_raster_bwd(
+__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 6 : 4))) void k_raster_bwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
     RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
@@ -740,43 +834,11 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     if (tid == 0) max_last = 0;
 
     // colour adjoint (Eq. image_formation)
-    float gA0 = 0, gA1 = 0, gA2 = 0, gV = 0, gD = 0, gN0 = 0, gN1 = 0, gN2 = 0;
     float cg[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) cg[k] = 0.f;
-    float Tr = 1.f;
-    int mylast = 0;
-    if (inside) {
-        float C[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, cb[3] = {0, 0, 0}, La[3] = {0, 0, 0};
-        if (colC) for (int k = 0; k < 9; ++k) C[k] = colC[9 * v + k];
-        if (colc) for (int k = 0; k < 3; ++k) cb[k] = colc[3 * v + k];
-        if (amb) for (int k = 0; k < 3; ++k) La[k] = amb[3 * v + k];
-        const float A[3] = {Ain[b3], Ain[b3 + P], Ain[b3 + 2 * P]};
-        const float Vp = HAS_VIS ? Vin[g] : 1.f;
-        float gI[3] = {0, 0, 0};
-        if (dI) { gI[0] = dI[b3]; gI[1] = dI[b3 + P]; gI[2] = dI[b3 + 2 * P]; }
-        float gs[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const float ca = C[3 * ch] * A[0] + C[3 * ch + 1] * A[1] + C[3 * ch + 2] * A[2] + cb[ch];
-            const float shade = HAS_VIS ? Vp + (1.f - Vp) * La[ch] : 1.f;
-            gs[ch] = gI[ch] * shade;
-            if (HAS_VIS) {
-                gV += gI[ch] * ca * (1.f - La[ch]);
-                cg[12 + ch] = gI[ch] * ca * (1.f - Vp);
-            }
-            cg[9 + ch] = gs[ch];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) cg[3 * ch + q] = gs[ch] * A[q];
-        }
-        gA0 = C[0] * gs[0] + C[3] * gs[1] + C[6] * gs[2];
-        gA1 = C[1] * gs[0] + C[4] * gs[1] + C[7] * gs[2];
-        gA2 = C[2] * gs[0] + C[5] * gs[1] + C[8] * gs[2];
-        if (dD) gD = dD[g];
-        if (dN) { gN0 = dN[b3]; gN1 = dN[b3 + P]; gN2 = dN[b3 + 2 * P]; }
-        Tr = Tin[g];
-        mylast = lastin[g];
-    }
+    const PixelAdjoint pa = pixel_adjoint<HAS_VIS>(inside, v, g, b3, P, colC, colc, amb, Ain, Vin,
+                                                   Tin, lastin, dI, dD, dN, cg);
+    float Tr = pa.Tr;
+    const int mylast = pa.last;
     {
         const float s = wave_transpose_reduce16(cg, lane);
         if ((lane & 3) == 0) red[wave][lane >> 2] = s;
@@ -861,57 +923,22 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
             }
             const int lim = row_last - (bb + c0);        // chunk records j < lim can contribute
             m &= lim >= 64 ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
-            // row-uniform walk, highest position first; the next record's fields are read
-            // from LDS while this one is processed
-            int jl = m != 0 ? 63 - (int)__builtin_clzll(m) : 0;
-            const float4 *Rn = lds + (c0 + jl) * kRecVec4;
-            float4 c0r = Rn[0], c1r = Rn[1], c2r = Rn[2], c3r = Rn[3];
+            // row-uniform walk, highest position first
             while (__ballot(m != 0) != 0) {
                 const bool act = m != 0;
+                const int jl = act ? 63 - (int)__builtin_clzll(m) : 0;
                 const int j = c0 + jl;
-                const float4 r0 = c0r, r1 = c1r, r2 = c2r, r3 = c3r;
                 if (act) m &= ~(1ull << jl);
-                jl = m != 0 ? 63 - (int)__builtin_clzll(m) : 0;
-                Rn = lds + (c0 + jl) * kRecVec4;
-                c0r = Rn[0]; c1r = Rn[1]; c2r = Rn[2]; c3r = Rn[3];
+                const float4 *R = lds + j * kRecVec4;
+                const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
                 // branch-free: every lane evaluates the row's record; lanes that do not
                 // contribute (outside [0, last) or alpha < alpha_min) get zero gradients
                 // and leave T and the suffix unchanged
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 const bool contrib = act && bb + j < mylast && e.alpha >= rc.alpha_min;
-                const float4 *R = lds + j * kRecVec4;
-                const float4 r4 = R[4], r5 = R[5];
-                const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
-                const float Tb = Tr * rom;
-                const float w = contrib ? e.alpha * Tb : 0.f;
-                const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
-                float gf = gA0 * r4.x + gA1 * r4.y + gA2 * r4.z + gD * z + gN0 * r5.x +
-                           gN1 * r5.y + gN2 * r5.z;
-                if (HAS_VIS) gf += gV * r4.w;
-                const float dal = contrib ? Tb * gf - gS * rom : 0.f;
-                gS += w * gf;
-                Tr = contrib ? Tb : Tr;
-                const float dz = w * gD;
                 float gr[16];
-                gr[G_AR] = w * gA0; gr[G_AG] = w * gA1; gr[G_AB] = w * gA2;
-                gr[G_NX] = w * gN0; gr[G_NY] = w * gN1; gr[G_NZ] = w * gN2;
-                gr[G_Z0] = dz;
-                const bool unclamped = e.oG < rc.alpha_max;
-                gr[G_O] = unclamped ? e.G * dal : 0.f;
-                const float dG = unclamped ? r3.x * dal : 0.f;
-                const float drho = -0.5f * e.G * dG;
-                const float du0 = 2.f * e.u0 * drho - r3.z * dz;
-                const float du1 = 2.f * e.u1 * drho - r3.w * dz;
-                gr[G_KU] = e.ub ? -e.u0 * dz : 0.f;
-                gr[G_KV] = e.ub ? -e.u1 * dz : 0.f;
-                gr[G_Q00] = e.ub ? du0 * e.dx : 0.f;
-                gr[G_Q01] = e.ub ? du0 * e.dy : 0.f;
-                gr[G_Q10] = e.ub ? du1 * e.dx : 0.f;
-                gr[G_Q11] = e.ub ? du1 * e.dy : 0.f;
-                const float ddx = e.ub ? r2.x * du0 + r2.z * du1 : two_is2 * e.dx * drho;
-                const float ddy = e.ub ? r2.y * du0 + r2.w * du1 : two_is2 * e.dy * drho;
-                gr[G_CX] = -ddx;
-                gr[G_CY] = -ddy;
+                pair_gradients(e, contrib, r2, r3, r4, r5, pa, HAS_VIS, two_is2, rc.alpha_max, Tr,
+                               gS, gr);
                 const uint64_t cb = __ballot(contrib);
                 if (cb == 0) continue;
                 const float sum = row_transpose_reduce16(gr, lane);
