@@ -646,17 +646,54 @@ __device__ __forceinline__ float wave_transpose_reduce16(float (&x)[16], int lan
 // Within one 16-lane row: 16 per-lane values -> lane i holds the row sum of value i.
 // Four levels, each pairing lanes that differ in one index bit (row mirror: bit 3,
 // half-row mirror: bit 2, quad permutes: bits 1 and 0); every level keeps the half of
-// the vector selected by that bit and adds the partner's copy of it.
+// the vector selected by that bit and adds the partner's copy of it.  The two halves of
+// the first two levels are whole 4-lane DPP banks (bank b = lanes 4b..4b+3 of a row), so
+// each kept value is one DPP add per half written under a bank mask; the compiler does
+// not see into the asm, so each block waits out the VALU-write -> DPP-read hazard itself.
 __device__ __forceinline__ float row_transpose_reduce16(const float (&x)[16], int lane)
 {
-    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+    const bool b1 = lane & 2, b0 = lane & 1;
     float y8[8], y4[4], y2[2];
+    // lanes 0-7 (banks 0, 1) keep values 0-7, lanes 8-15 (banks 2, 3) values 8-15; y8[k]
+    // starts as x[k + 8] and is overwritten in place (an instruction reads its sources
+    // before it writes)
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        y8[k] = (b3 ? x[k + 8] : x[k]) + dpp<0x140>(b3 ? x[k] : x[k + 8]);
+    for (int k = 0; k < 8; ++k) y8[k] = x[k + 8];
+    asm("s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %0, %8, %8 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %1, %9, %9 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %2, %10, %10 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %3, %3, %3 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %3, %11, %11 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %4, %4, %4 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %4, %12, %12 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %5, %5, %5 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %5, %13, %13 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %6, %6, %6 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %6, %14, %14 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %7, %7, %7 row_mirror row_mask:0xf bank_mask:0xc\n\t"
+        "v_add_f32_dpp %7, %15, %15 row_mirror row_mask:0xf bank_mask:0x3\n\t"
+        : "+v"(y8[0]), "+v"(y8[1]), "+v"(y8[2]), "+v"(y8[3]), "+v"(y8[4]), "+v"(y8[5]),
+          "+v"(y8[6]), "+v"(y8[7])
+        : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(x[6]), "v"(x[7]));
+    // lanes with bit 2 clear (banks 0, 2) keep values 0-3, the others 4-7
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        y4[k] = (b2 ? y8[k + 4] : y8[k]) + dpp<0x141>(b2 ? y8[k] : y8[k + 4]);
+    for (int k = 0; k < 4; ++k) y4[k] = y8[k + 4];
+    asm("s_nop 1\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %0, %4, %4 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %1, %5, %5 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %2, %6, %6 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "v_add_f32_dpp %3, %3, %3 row_half_mirror row_mask:0xf bank_mask:0xa\n\t"
+        "v_add_f32_dpp %3, %7, %7 row_half_mirror row_mask:0xf bank_mask:0x5\n\t"
+        "s_nop 1"
+        : "+v"(y4[0]), "+v"(y4[1]), "+v"(y4[2]), "+v"(y4[3])
+        : "v"(y8[0]), "v"(y8[1]), "v"(y8[2]), "v"(y8[3]));
 #pragma unroll
     for (int k = 0; k < 2; ++k)
         y2[k] = (b1 ? y4[k + 2] : y4[k]) + dpp<0x4E>(b1 ? y4[k] : y4[k + 2]);
