@@ -449,15 +449,10 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
             uint64_t m = chunk_mask(head, lane < cnt, wx0, wy0, lane);
             if (done) m = 0;
             unsigned long long cmc = 0ull;
-            // the next covered record's fields are read from LDS while this one is evaluated
-            int j = c0 + (m != 0 ? (int)__builtin_ctzll(m) : 0);
-            float4 c0r = lds[j], c1r = lds[B + j], c2r = lds[2 * B + j], c3r = lds[3 * B + j];
             while (m != 0) {
+                const int jc = c0 + (int)__builtin_ctzll(m);
                 m &= m - 1;
-                const int jc = j;
-                const float4 r0 = c0r, r1 = c1r, r2 = c2r, r3 = c3r;
-                j = c0 + (m != 0 ? (int)__builtin_ctzll(m) : 0);
-                c0r = lds[j]; c1r = lds[B + j]; c2r = lds[2 * B + j]; c3r = lds[3 * B + j];
+                const float4 r0 = lds[jc], r1 = lds[B + jc], r2 = lds[2 * B + jc], r3 = lds[3 * B + jc];
                 ++neval;
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 // branch-free: a skipped pair accumulates with weight 0 (w * x + a == a
