@@ -22,16 +22,14 @@ def scene_tiny(seed=7, views=((45, 38), (33, 29), (70, 17)), n=400, **kw):
 
 
 # ---------------------------------------------------------------- binning
-@pytest.mark.parametrize("ts", [8, 16, 32])
-def test_binning_bit_exact(ts):
-    sc = scene_tiny(seed=3, views=((71, 45), (40, 40), (17, 90)), n=700)
+def check_binning(sc, ts):
     plan, surf, views = make_plan(sc, ts=ts)
     plan.forward(surf, views)
     b = plan.debug_binning(0)
     st = oracle_settings(ts=ts)
     order = oracle.depth_order(sc["surfels"]["mean"], sc["b_z"])
     np.testing.assert_array_equal(b["order"].astype(np.int64), order)
-    toff = 0
+    toff, pairs = 0, []
     for v, (W, H) in enumerate(zip(sc["width"], sc["height"])):
         B, bb = oracle.view_camera(sc, v)
         _, _, _, tiles = oracle.binning(sc, B, bb, int(W), int(H), ts, st)
@@ -43,8 +41,34 @@ def test_binning_bit_exact(ts):
             g = b["lists"][gr[t, 0]:gr[t, 1]].astype(np.int64)
             e = flat[ranges[t, 0]:ranges[t, 1]]
             np.testing.assert_array_equal(g, e, err_msg=f"view {v} tile {t}")
+        empty = ranges[:, 1] == ranges[:, 0]
+        assert np.all(gr[empty] == 0), f"view {v}: empty tiles carry (0, 0)"
         toff += nt
+        pairs.append(len(flat))
     assert toff == b["ranges"].shape[0]
+    return pairs
+
+
+@pytest.mark.parametrize("ts", [8, 16, 32])
+def test_binning_bit_exact(ts):
+    check_binning(scene_tiny(seed=3, views=((71, 45), (40, 40), (17, 90)), n=700), ts)
+
+
+def test_binning_bit_exact_with_a_view_that_sees_nothing():
+    """A view whose camera is shifted far off the scene has no pairs: its run in the
+    per-view tile sort is empty, and the views after it must still land in place."""
+    sc = scene_tiny(seed=4, views=((52, 41), (40, 40), (33, 58)), n=600)
+    sc["Fxy"] = sc["Fxy"].copy()
+    sc["Fxy"][1, :, 3] += 1.0e5
+    pairs = check_binning(sc, 8)
+    assert pairs[1] == 0 and pairs[0] > 0 and pairs[2] > 0
+
+
+def test_binning_bit_exact_many_sort_blocks_per_view():
+    """Views whose pair runs span many 4096-pair sort blocks (and 2 radix passes)."""
+    sc = scene_tiny(seed=9, views=((300, 221), (257, 311)), n=30000)
+    pairs = check_binning(sc, 8)
+    assert min(pairs) > 5 * 4096
 
 
 def test_records_centre_matches_fp64():
