@@ -55,6 +55,7 @@ struct Layout {
     size_t pk_a, pv_a, pk_b, pv_b, ranges_main, recgrad, colour_parts, dF_parts;
     size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
     size_t sun_depth, bounds, radix_temp, tmask_sun, cmask, cmask_bytes, stat_main, stat_sun;
+    size_t inv_order, vis_rank;
     size_t total;
 };
 
@@ -203,6 +204,8 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.bounds = take((size_t)bounds_blocks(p->n) * 6 * 8);
     L.radix_temp = take(radix_temp_bytes(std::max<int64_t>(p->n, std::max(cm, cs)), p->nv));
     L.tmask_sun = take((size_t)p->tiles_sun_max * 4);
+    L.inv_order = take(n * 4);
+    L.vis_rank = take(vn * 4);
     // forward -> backward contributor masks of 8x8 tiles (other sizes use the box test)
     L.cmask_bytes = p->st.tile_size == 8 ? cmask_words(cm, p->tiles_main_max) * 8 : 0;
     L.cmask = take(L.cmask_bytes);
@@ -305,8 +308,14 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
     const int64_t cap = sun ? p->cap_sun : p->cap_main;
     {
         StageScope scope(p, sun ? SS_STAGE_SUN_PROJECT : SS_STAGE_PROJECT, st);
-        SS_HIP(launch_project(sorted, p->n, order, p->nv, views, v->Fxy, sun ? nullptr : v->dF,
-                              sun ? p->at<SunCam>(L.suncam) : nullptr, sun ? nullptr : vis,
+        const float *vis_rank = nullptr;
+        if (!sun && vis) {
+            SS_HIP(launch_vis_to_rank(vis, p->n, p->nv, order, p->at<uint32_t>(L.inv_order),
+                                      p->at<float>(L.vis_rank), st));
+            vis_rank = p->at<float>(L.vis_rank);
+        }
+        SS_HIP(launch_project(sorted, p->n, p->nv, views, v->Fxy, sun ? nullptr : v->dF,
+                              sun ? p->at<SunCam>(L.suncam) : nullptr, vis_rank,
                               v->b_z, p->st.tile_size, rc, rec, tiles, counts, tmask, st));
     }
     StageScope scope(p, sun ? SS_STAGE_SUN_BIN : SS_STAGE_BIN, st);

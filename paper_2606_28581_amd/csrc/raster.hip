@@ -82,19 +82,22 @@ hipError_t launch_gather_params(const uint32_t *order, const SurfelPtrs &s, floa
 //   {T w : |w|^2 <= rho_max} has x half-extent r |T row 0|, the low-pass disk radius
 //   sigma r; pixel i is in the box iff i + 0.5 lies within the half-extent of c.
 __global__ __launch_bounds__(256) void k_project(
-    const float4 *__restrict__ sp, int64_t n, const uint32_t *__restrict__ order,
+    const float4 *__restrict__ sp, int64_t n, int32_t nv,
     const ViewDesc *__restrict__ views, const float *__restrict__ Fxy,
     const float *__restrict__ dF, const SunCam *__restrict__ sun,
-    const float *__restrict__ vis, float bz, int ts, RasterConsts rc,
+    const float *__restrict__ vis_rank, float bz, int ts, RasterConsts rc,
     float4 *__restrict__ rec, short4 *__restrict__ tiles, uint32_t *__restrict__ counts,
     const uint32_t *__restrict__ tmask)
 {
-    // the block's 256 records are staged in LDS and written back as one contiguous run
+    // the block's 256 records are staged in LDS and written back as one contiguous run.
+    // Blocks run view-innermost (block = rank block x views + view), in XCD-contiguous
+    // order, so the views of one rank block share the surfel parameters in one L2.
     __shared__ float4 srec[256 * kRecVec4];
-    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t L = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int v = (int)(L % nv);
+    const int64_t r0 = (L / nv) * blockDim.x;
     const bool valid = r0 + threadIdx.x < n;
     const int64_t r = valid ? r0 + threadIdx.x : n - 1;   // lanes past the end repeat the last
-    const int v = blockIdx.y;
     const ViewDesc vd = views[v];
     double B[2][3], b[2];
     if (sun) {
@@ -201,8 +204,7 @@ __global__ __launch_bounds__(256) void k_project(
                        deg ? inf : 0.f, filt ? 0.f : inf);
     R[2] = make_float4((float)Q[0][0], (float)Q[0][1], (float)Q[1][0], (float)Q[1][1]);
     R[3] = make_float4((float)o, (float)((double)bz - p[2]), (float)M[2][0], (float)M[2][1]);
-    const uint32_t oi = order[r];
-    const float vv = (vis && oi < n) ? vis[(int64_t)v * n + oi] : 1.f;
+    const float vv = vis_rank ? vis_rank[r * nv + v] : 1.f;
     R[4] = make_float4(pd.x, pd.y, pd.z, vv);
     const double s = nsign / mn;
     R[5] = make_float4((float)(s * m[0]), (float)(s * m[1]), (float)(s * m[2]), (float)nsign);
@@ -212,17 +214,70 @@ __global__ __launch_bounds__(256) void k_project(
     for (int i = threadIdx.x; i < nrec * kRecVec4; i += blockDim.x) dst[i] = srec[i];
 }
 
-hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order, int32_t nv,
-                          const ViewDesc *views, const float *Fxy, const float *dF,
-                          const SunCam *sun, const float *vis, float bz, int ts,
-                          const RasterConsts &rc, float *rec, short4 *tiles, uint32_t *counts,
-                          const uint32_t *tmask, hipStream_t st)
+hipError_t launch_project(const float *sorted, int64_t n, int32_t nv, const ViewDesc *views,
+                          const float *Fxy, const float *dF, const SunCam *sun,
+                          const float *vis_rank, float bz, int ts, const RasterConsts &rc,
+                          float *rec, short4 *tiles, uint32_t *counts, const uint32_t *tmask,
+                          hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256), 0,
-                       st, reinterpret_cast<const float4 *>(sorted), n, order, views, Fxy, dF,
-                       sun, vis, bz, ts, rc, reinterpret_cast<float4 *>(rec), tiles, counts,
+    const int64_t blocks = (n + 255) / 256 * nv;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const float4 *>(sorted), n, nv, views, Fxy, dF, sun,
+                       vis_rank, bz, ts, rc, reinterpret_cast<float4 *>(rec), tiles, counts,
                        tmask);
+    return hipGetLastError();
+}
+
+// Visibility arrives per view in surfel order; the projection reads it per rank.  The
+// depth order is one permutation for all views, so one pass over surfels k (coalesced
+// reads of every view's vis[v][k]) writes the nv values of surfel k contiguously at its
+// rank: out[rank(k) * nv + v].
+__global__ void k_inverse_order(const uint32_t *__restrict__ order, int64_t n,
+                                uint32_t *__restrict__ rank)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint32_t k = order[r];
+    if (k < n) rank[k] = (uint32_t)r;
+}
+
+// A block transposes a chunk of surfels through LDS (rows padded to nv + 1 floats):
+// reads run along k per view, writes along v per surfel (one contiguous run each).
+__global__ __launch_bounds__(256) void k_vis_to_rank(const float *__restrict__ vis, int64_t n,
+                                                     int32_t nv, int chunk,
+                                                     const uint32_t *__restrict__ rank,
+                                                     float *__restrict__ out)
+{
+    extern __shared__ float sv[];
+    const int64_t k0 = (int64_t)blockIdx.x * chunk;
+    const int cnt = (int)min((int64_t)chunk, n - k0);
+    const int row = nv + 1;
+    for (int i = threadIdx.x; i < cnt * nv; i += blockDim.x) {
+        const int v = i / cnt, kk = i - v * cnt;
+        sv[kk * row + v] = vis[(int64_t)v * n + k0 + kk];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt * nv; i += blockDim.x) {
+        const int kk = i / nv, v = i - kk * nv;
+        const uint32_t r = min(rank[k0 + kk], (uint32_t)(n - 1));
+        out[(int64_t)r * nv + v] = sv[kk * row + v];
+    }
+}
+
+hipError_t launch_vis_to_rank(const float *vis, int64_t n, int32_t nv, const uint32_t *order,
+                              uint32_t *rank, float *out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_inverse_order, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, order,
+                       n, rank);
+    // chunk x (nv + 1) floats of LDS, at most 64 KB
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, 16384 / (nv + 1)));
+    const size_t lds = (size_t)chunk * (nv + 1) * sizeof(float);
+    hipLaunchKernelGGL(k_vis_to_rank, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(256), lds, st,
+                       vis, n, nv, chunk, rank, out);
     return hipGetLastError();
 }
 
@@ -332,16 +387,6 @@ __device__ __forceinline__ bool box_hits(float bx, float by, int wx0, int wy0)
     return xlo <= wx0 + 7 && xhi >= wx0 && ylo <= wy0 + 7 && yhi >= wy0;
 }
 
-// Workgroups go round-robin to the 8 XCDs, each with its own L2.  Handing every XCD a
-// contiguous run of tiles keeps neighbouring tiles, which share most of their records,
-// under one L2.  Bijective on [0, nblocks).
-__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
-{
-    constexpr int kXcd = 8;
-    const int q = nblocks / kXcd, r = nblocks % kXcd;
-    const int x = bid % kXcd, i = bid / kXcd;
-    return x * q + min(x, r) + i;
-}
 
 // ------------------------------------------------------------- per-pixel coverage
 // Records of a batch sit in LDS as structure of arrays by float4 group: group g of

@@ -124,6 +124,7 @@ __global__ void k_shadow_query(const float *__restrict__ mean, int64_t n,
                                int32_t S, float bz, float esm_c, float esm_bias,
                                float *__restrict__ vis, float band)
 {
+    // view-outermost grid: the blocks in flight read one view's sun map, which stays in L2
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     if (k >= n) return;

@@ -73,6 +73,17 @@ struct SurfelPtrs {
     int64_t n;
 };
 
+// Workgroups go round-robin to the 8 XCDs, each with its own L2.  Handing every XCD a
+// contiguous run of tiles keeps neighbouring tiles (or the views of one chunk of surfels)
+// under one L2.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+{
+    constexpr int kXcd = 8;
+    const int q = nblocks / kXcd, r = nblocks % kXcd;
+    const int x = bid % kXcd, i = bid / kXcd;
+    return x * q + min(x, r) + i;
+}
+
 // ------------------------------------------------------------------- launchers
 // sort.hip
 // Temp bytes of radix_sort_pairs for up to max_items items in up to max_segs segments.
@@ -114,11 +125,16 @@ hipError_t launch_depth_keys(const float *mean, int64_t n, float bz, uint32_t *k
                              uint32_t *vals, hipStream_t st);
 hipError_t launch_gather_params(const uint32_t *order, const SurfelPtrs &s, float *out,
                                 hipStream_t st);
-hipError_t launch_project(const float *sorted, int64_t n, const uint32_t *order, int32_t nv,
-                          const ViewDesc *views, const float *Fxy, const float *dF,
-                          const SunCam *sun, const float *vis, float bz, int ts,
-                          const RasterConsts &rc, float *rec, short4 *tiles, uint32_t *counts,
-                          const uint32_t *tmask, hipStream_t st);
+// vis_rank: visibility per (rank, view), [n][nv] (see launch_vis_to_rank), or NULL.
+hipError_t launch_project(const float *sorted, int64_t n, int32_t nv, const ViewDesc *views,
+                          const float *Fxy, const float *dF, const SunCam *sun,
+                          const float *vis_rank, float bz, int ts, const RasterConsts &rc,
+                          float *rec, short4 *tiles, uint32_t *counts, const uint32_t *tmask,
+                          hipStream_t st);
+// out[rank * nv + v] = vis[v * n + order[rank]]; rank (n entries) is scratch that ends up
+// holding the inverse of order.
+hipError_t launch_vis_to_rank(const float *vis, int64_t n, int32_t nv, const uint32_t *order,
+                              uint32_t *rank, float *out, hipStream_t st);
 hipError_t launch_emit(const uint32_t *order, int64_t n, int32_t nv, const ViewDesc *views,
                        const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
                        uint64_t cap, uint32_t *keys, uint32_t *vals, const uint32_t *tmask,
