@@ -651,7 +651,7 @@ ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
     {
         StageScope scope(p, SS_STAGE_PROJECT_BWD, st);
         SS_HIP(launch_project_bwd(p->at<float>(L.sorted_main), p->n, p->order_main, p->nv, v->Fxy,
-                                  v->dF, p->at<float>(L.rec_main), recgrad, d_mean, d_t_u, d_t_v,
+                                  v->dF, consts(p->st).det_rel_eps_d, recgrad, d_mean, d_t_u, d_t_v,
                                   d_scale, d_opacity, d_albedo, p->at<float>(L.dF_parts), st));
     }
     StageScope scope(p, SS_STAGE_REDUCE, st);

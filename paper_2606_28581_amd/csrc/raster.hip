@@ -73,6 +73,49 @@ hipError_t launch_gather_params(const uint32_t *order, const SurfelPtrs &s, floa
     return hipGetLastError();
 }
 
+// Affine projection of one surfel's tangent frame (Sec. 3.2, Eqs. affine2dgs_uv2screen,
+// affine2dgs_Qq): M = [s_u t_u, s_v t_v], T = B M, Q = T^-1 (zero when T is degenerate),
+// and the sign that orients the normal m = t_u x t_v against the viewing direction
+// d = B_x x B_y taken looking down (d_z < 0).  FP64; the projection and its backward both
+// call it, so the backward sees the very Q and sign the forward used.
+struct SurfelAffine {
+    double M[3][2], T[2][2], Q[2][2], m[3];
+    double nsign;
+    bool deg;
+};
+
+__device__ __forceinline__ SurfelAffine surfel_affine(const double (&B)[2][3], const double (&tu)[3],
+                                                      const double (&tv)[3], double su, double sv,
+                                                      double det_rel_eps)
+{
+    SurfelAffine a;
+    for (int i = 0; i < 3; ++i) { a.M[i][0] = su * tu[i]; a.M[i][1] = sv * tv[i]; }
+    for (int row = 0; row < 2; ++row)
+        for (int q = 0; q < 2; ++q) {
+            double acc = 0.0;
+            for (int i = 0; i < 3; ++i) acc += B[row][i] * a.M[i][q];
+            a.T[row][q] = acc;
+        }
+    const double(&T)[2][2] = a.T;
+    const double det = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+    const double fro2 = T[0][0] * T[0][0] + T[0][1] * T[0][1] + T[1][0] * T[1][0] + T[1][1] * T[1][1];
+    a.deg = !(fabs(det) > det_rel_eps * fro2);
+    a.Q[0][0] = a.Q[0][1] = a.Q[1][0] = a.Q[1][1] = 0.0;
+    if (!a.deg) {
+        a.Q[0][0] = T[1][1] / det; a.Q[0][1] = -T[0][1] / det;
+        a.Q[1][0] = -T[1][0] / det; a.Q[1][1] = T[0][0] / det;
+    }
+    a.m[0] = tu[1] * tv[2] - tu[2] * tv[1];
+    a.m[1] = tu[2] * tv[0] - tu[0] * tv[2];
+    a.m[2] = tu[0] * tv[1] - tu[1] * tv[0];
+    double dvec[3] = {B[0][1] * B[1][2] - B[0][2] * B[1][1], B[0][2] * B[1][0] - B[0][0] * B[1][2],
+                      B[0][0] * B[1][1] - B[0][1] * B[1][0]};
+    if (dvec[2] > 0) { dvec[0] = -dvec[0]; dvec[1] = -dvec[1]; dvec[2] = -dvec[2]; }
+    const double nd = a.m[0] * dvec[0] + a.m[1] * dvec[1] + a.m[2] * dvec[2];
+    a.nsign = nd > 0 ? -1.0 : 1.0;
+    return a;
+}
+
 // ------------------------------------------------------------------- projection
 // One thread per (rank r, view v).  Geometry in FP64 (the binning contract: tile
 // ranges must be bit-identical to an FP64 reference), records rounded to FP32.
@@ -116,36 +159,20 @@ __global__ __launch_bounds__(256) void k_project(
     const double tu[3] = {pa.w, pb.x, pb.y};
     const double tv[3] = {pb.z, pb.w, pc.x};
     const double su = pc.y, sv = pc.z, o = pc.w;
-    double M[3][2];
-    for (int i = 0; i < 3; ++i) { M[i][0] = su * tu[i]; M[i][1] = sv * tv[i]; }
-    double T[2][2], c[2];
+    const SurfelAffine sa = surfel_affine(B, tu, tv, su, sv, rc.det_rel_eps_d);
+    const double(&M)[3][2] = sa.M;
+    const double(&T)[2][2] = sa.T;
+    const double(&Q)[2][2] = sa.Q;
+    const double(&m)[3] = sa.m;
+    const bool deg = sa.deg;
+    const double nsign = sa.nsign;
+    double c[2];
     for (int row = 0; row < 2; ++row) {
-        for (int q = 0; q < 2; ++q) {
-            double acc = 0.0;
-            for (int i = 0; i < 3; ++i) acc += B[row][i] * M[i][q];
-            T[row][q] = acc;
-        }
         double acc = b[row];
         for (int i = 0; i < 3; ++i) acc += B[row][i] * p[i];
         c[row] = acc;
     }
-    const double det = T[0][0] * T[1][1] - T[0][1] * T[1][0];
-    const double fro2 = T[0][0] * T[0][0] + T[0][1] * T[0][1] + T[1][0] * T[1][0] + T[1][1] * T[1][1];
-    const bool deg = !(fabs(det) > rc.det_rel_eps_d * fro2);
-    double Q[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    if (!deg) {
-        Q[0][0] = T[1][1] / det; Q[0][1] = -T[0][1] / det;
-        Q[1][0] = -T[1][0] / det; Q[1][1] = T[0][0] / det;
-    }
     const bool filt = (rc.lowpass_mode == 0) || deg;
-    // normal m = t_u x t_v, oriented against d = B_x x B_y taken looking down (d_z < 0)
-    double m[3] = {tu[1] * tv[2] - tu[2] * tv[1], tu[2] * tv[0] - tu[0] * tv[2],
-                   tu[0] * tv[1] - tu[1] * tv[0]};
-    double dvec[3] = {B[0][1] * B[1][2] - B[0][2] * B[1][1], B[0][2] * B[1][0] - B[0][0] * B[1][2],
-                      B[0][0] * B[1][1] - B[0][1] * B[1][0]};
-    if (dvec[2] > 0) { dvec[0] = -dvec[0]; dvec[1] = -dvec[1]; dvec[2] = -dvec[2]; }
-    const double nd = m[0] * dvec[0] + m[1] * dvec[1] + m[2] * dvec[2];
-    const double nsign = nd > 0 ? -1.0 : 1.0;
     const double mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
     // support box -> pixel and tile ranges
     int ilo = 0, ihi = -1, jlo = 0, jhi = -1;
@@ -1119,8 +1146,8 @@ constexpr int kPbThreads = 256;
 
 __global__ __launch_bounds__(kPbThreads) void k_project_bwd(
     const float4 *__restrict__ sp, int64_t n, const uint32_t *__restrict__ order, int32_t nv,
-    const float *__restrict__ Fxy, const float *__restrict__ dF,
-    const float4 *__restrict__ rec, const float4 *__restrict__ recgrad,
+    const float *__restrict__ Fxy, const float *__restrict__ dF, double det_rel_eps,
+    const float4 *__restrict__ recgrad,
     float *__restrict__ d_mean, float *__restrict__ d_tu, float *__restrict__ d_tv,
     float *__restrict__ d_scale, float *__restrict__ d_opac, float *__restrict__ d_alb,
     float *__restrict__ dF_partials)
@@ -1144,11 +1171,16 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(
     const float mn = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
     float gp[3] = {0, 0, 0}, gtu[3] = {0, 0, 0}, gtv[3] = {0, 0, 0}, gsu = 0, gsv = 0, go = 0;
     float ga[3] = {0, 0, 0};
+    const double pd_tu[3] = {tu[0], tu[1], tu[2]}, pd_tv[3] = {tv[0], tv[1], tv[2]};
     for (int v = 0; v < nv; ++v) {
         float B[2][3];
+        double Bd[2][3];
         for (int row = 0; row < 2; ++row)
-            for (int q = 0; q < 3; ++q)
+            for (int q = 0; q < 3; ++q) {
                 B[row][q] = Fxy[8 * v + 4 * row + q] + (dF ? dF[8 * v + 4 * row + q] : 0.f);
+                Bd[row][q] = (double)Fxy[8 * v + 4 * row + q] +
+                             (dF ? (double)dF[8 * v + 4 * row + q] : 0.0);
+            }
         float x[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) x[k] = 0.f;
@@ -1159,9 +1191,11 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(
             const float dc[2] = {g0.x, g0.y};
             const float dQ[2][2] = {{g0.z, g0.w}, {g1.x, g1.y}};
             const float dz0 = g1.z, dk0 = g1.w, dk1 = g2.x, dO = g2.y;
-            const float4 Qv = rec[6 * slot + 2];
-            const float nsign = rec[6 * slot + 5].w;
-            const float Q[2][2] = {{Qv.x, Qv.y}, {Qv.z, Qv.w}};
+            // Q and the normal's sign exactly as the projection stored them in the record
+            const SurfelAffine sa = surfel_affine(Bd, pd_tu, pd_tv, (double)su, (double)sv, det_rel_eps);
+            const float nsign = (float)sa.nsign;
+            const float Q[2][2] = {{(float)sa.Q[0][0], (float)sa.Q[0][1]},
+                                   {(float)sa.Q[1][0], (float)sa.Q[1][1]}};
             float t1[2][2], dT[2][2];
             for (int a = 0; a < 2; ++a)
                 for (int q = 0; q < 2; ++q) t1[a][q] = Q[0][a] * dQ[0][q] + Q[1][a] * dQ[1][q];
@@ -1231,7 +1265,7 @@ __global__ __launch_bounds__(kPbThreads) void k_project_bwd(
 int project_bwd_blocks(int64_t n) { return (int)((n + kPbThreads - 1) / kPbThreads); }
 
 hipError_t launch_project_bwd(const float *sorted, int64_t n, const uint32_t *order,
-                              int32_t nv, const float *Fxy, const float *dF, const float *rec,
+                              int32_t nv, const float *Fxy, const float *dF, double det_rel_eps,
                               const float *recgrad, float *d_mean, float *d_tu, float *d_tv,
                               float *d_scale, float *d_opac, float *d_alb, float *dF_partials,
                               hipStream_t st)
@@ -1239,8 +1273,7 @@ hipError_t launch_project_bwd(const float *sorted, int64_t n, const uint32_t *or
     const int nb = project_bwd_blocks(n);
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)nb), dim3(kPbThreads), 0, st,
-                       reinterpret_cast<const float4 *>(sorted), n, order, nv, Fxy, dF,
-                       reinterpret_cast<const float4 *>(rec),
+                       reinterpret_cast<const float4 *>(sorted), n, order, nv, Fxy, dF, det_rel_eps,
                        reinterpret_cast<const float4 *>(recgrad), d_mean, d_tu, d_tv, d_scale,
                        d_opac, d_alb, dF_partials);
     return hipGetLastError();

@@ -163,7 +163,7 @@ hipError_t launch_colour_reduce(const float *partials, int32_t nv, const ViewDes
                                 float *d_colC, float *d_colc, float *d_amb, hipStream_t st);
 int project_bwd_blocks(int64_t n);
 hipError_t launch_project_bwd(const float *sorted, int64_t n, const uint32_t *order,
-                              int32_t nv, const float *Fxy, const float *dF, const float *rec,
+                              int32_t nv, const float *Fxy, const float *dF, double det_rel_eps,
                               const float *recgrad, float *d_mean, float *d_tu, float *d_tv,
                               float *d_scale, float *d_opac, float *d_alb, float *dF_partials,
                               hipStream_t st);
