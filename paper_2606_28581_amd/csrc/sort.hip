@@ -340,11 +340,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
         const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
         const int64_t wbase = br.lo + (int64_t)w * (kSortItems * kWave);
         const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+        // all of the wave's keys are loaded before any is counted
+        uint32_t key[kSortItems];
+#pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             const int64_t i = wbase + it * kWave + lane;
-            const bool valid = i < br.hi;
-            if (__ballot(valid) == 0) break;
-            const uint32_t d = valid ? ((keys[i] - br.base) >> shift) & 255u : 0u;
+            key[it] = i < br.hi ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const bool valid = wbase + it * kWave + lane < br.hi;
+            const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
             // one LDS add per group of lanes with the same digit (its lowest lane)
             const uint64_t m = digit_peers(d, valid, nbits);
             if (valid && (m & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(m));
@@ -410,6 +416,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int64_t cap, int64_t n_host, int shift, int nbits, uint32_t *ranges, int64_t nkeys)
 {
     __shared__ uint32_t wcnt[kSortWaves][256];
+    __shared__ uint32_t wsink[kSortWaves][kWave];  // target of the lanes that are not group leaders
     __shared__ uint32_t dbase[256];          // block-local start of each digit's run
     __shared__ uint32_t gshift[256];         // global start minus local start, per digit
     __shared__ uint32_t lds_w[kSortWaves];
@@ -428,13 +435,22 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const bool valid = i < br.hi;
         key[it] = valid ? kin[i] : 0u;
         val[it] = valid ? vin[i] : 0u;
+    }
+    // stable ranks: per item row, the lowest lane of each equal-digit group adds the group
+    // size to the wave's running count of that digit and receives the count before it (LDS
+    // atomics of one wave take effect in issue order, row after row); the other lanes add
+    // to a private word so that no two lanes of an instruction share an address
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const bool valid = wbase + it * kWave + lane < br.hi;
         const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
         const uint64_t m = digit_peers(d, valid, nbits);
         const uint32_t before = __popcll(m & lt_mask);
-        const uint32_t cur = wcnt[w][d];
-        rank[it] = cur + before;
-        if (valid && before == 0) wcnt[w][d] = cur + (uint32_t)__popcll(m);
-        __builtin_amdgcn_wave_barrier();
+        const bool leader = valid && before == 0;
+        uint32_t *cnt = leader ? &wcnt[w][d] : &wsink[w][lane];
+        const uint32_t old = atomicAdd(cnt, leader ? (uint32_t)__popcll(m) : 0u);
+        const int from = m != 0 ? (int)__builtin_ctzll(m) : lane;
+        rank[it] = (uint32_t)__shfl((int)old, from, kWave) + before;
     }
     __syncthreads();
     {
