@@ -331,11 +331,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
     const uint64_t b_hi = max(b_lo, (uint64_t)offsets[(int64_t)v * n + rend]);
     const bool staged = b_hi - b_lo <= (uint64_t)kEmitStage;   // uniform over the block
     if (r < n) {
+        // the three loads are independent: issue them together
         const int64_t slot = (int64_t)v * n + r;
-        if (counts[slot] != 0) {
-            const short4 t = tiles[slot];
+        const uint32_t cnt = counts[slot];
+        const short4 t = tiles[slot];
+        uint64_t pos = offsets[slot];
+        if (cnt != 0) {
             const ViewDesc vd = views[v];
-            uint64_t pos = offsets[slot];
             for (int ty = t.z; ty <= t.w; ++ty)
                 for (int tx = t.x; tx <= t.y; ++tx) {
                     const uint32_t key = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
