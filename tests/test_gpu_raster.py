@@ -149,12 +149,15 @@ def check_backward(sc, plan, surf, views, out, ref, vis=None, tol=1e-3):
     return errs
 
 
-def test_backward_multiview_with_colour_and_vis():
+@pytest.mark.parametrize("ts,batch", [(16, 64), (8, 64), (8, 32)])
+def test_backward_multiview_with_colour_and_vis(ts, batch):
+    """8x8 tiles take the contributor-mask walk (batch 32: the backward's batches then
+    split the forward's 64-position mask words)."""
     sc = scene_tiny(seed=13)
     vis = np.random.default_rng(2).uniform(size=(3, 400)).astype(np.float32)
-    plan, surf, views = make_plan(sc)
+    plan, surf, views = make_plan(sc, ts=ts, batch=batch)
     out = plan.forward(surf, views, torch.as_tensor(vis, device="cuda"))
-    ref = oracle.forward(sc, oracle_settings(), vis=vis)
+    ref = oracle.forward(sc, oracle_settings(ts=ts), vis=vis)
     check_backward(sc, plan, surf, views, out, ref, vis=vis)
 
 
