@@ -3,11 +3,17 @@
 // depth, organise into tiles).
 //
 // Radix sort: 8-bit digits, 256 threads x 16 items = 4096 items per block.
-//   hist    : per-block digit histogram in LDS -> hist[digit * nblocks + block]
+//   hist    : per-block digit histogram in LDS (one add per group of lanes holding the
+//             same digit) -> hist[digit * nblocks + block], or per segment (below)
 //   scan    : exclusive scan of hist (digit-major) -> global base of (digit, block)
 //   scatter : per-wave stable multisplit with 8 ballots per item (lanes holding the
-//             same digit form a mask; rank = popcount of lower lanes in the mask),
-//             running per-wave digit counters in LDS, then a prefix over the 4 waves.
+//             same digit form a mask; rank = popcount of lower lanes in the mask); the
+//             group's lowest lane adds the group size to the wave's running count of
+//             that digit in LDS and hands the old count to the group, then a prefix
+//             over the 4 waves places each digit's run inside the block.
+// Tile bucketing sorts within segments (one per view) on key minus the segment's base,
+// so the number of passes follows the largest view's tile count; its last pass also
+// writes each tile's [begin, end) range.
 // Item counts may live in device memory (pair counts are data dependent), so grids
 // are sized by capacity and blocks past the live count exit at once.
 #include "ss_internal.h"
