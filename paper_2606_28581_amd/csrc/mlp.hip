@@ -28,11 +28,12 @@ constexpr int kMlpThreads = 256;
 constexpr int kMlpWaves = kMlpThreads / 64;
 constexpr int kHStride = 72;        // bf16 row stride of the per-wave activation tile
 
+// FP32 -> BF16, round to nearest even (gfx950 converts in hardware, two values per
+// instruction when the compiler pairs them)
 __device__ __forceinline__ u16 f2bf(float x)
 {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (u16)(u >> 16);
+    const __bf16 h = (__bf16)x;
+    return __builtin_bit_cast(u16, h);
 }
 __device__ __forceinline__ float bf2f(u16 b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -78,8 +79,11 @@ __device__ __forceinline__ void feature_chunk(const float ph[3], float cphi, flo
             const int k = 4 * g + q;                       // frequency
             const float x = x0 * (float)(1u << k);        // exact: power-of-two scaling
             const float r = x - 2.f * rintf(0.5f * x);    // exact reduction to [-1, 1]
-            float s, c;
-            sincospif(r, &s, &c);
+            // sin(pi r), cos(pi r) with the hardware sine and cosine, whose argument is in
+            // revolutions (r / 2, exact); their error is far below the BF16 rounding that
+            // follows
+            const float s = __builtin_amdgcn_sinf(0.5f * r);
+            const float c = __builtin_amdgcn_cosf(0.5f * r);
             out.h[2 * q] = f2bf(s);
             out.h[2 * q + 1] = f2bf(c);
         }
@@ -209,10 +213,11 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(
             ph[0] = __fmul_rn(__fsub_rn(pts[3 * ip], nz.cx), nz.inv_half);
             ph[1] = __fmul_rn(__fsub_rn(pts[3 * ip + 1], nz.cy), nz.inv_half);
             ph[2] = __fmul_rn(__fsub_rn(pts[3 * ip + 2], nz.cz), nz.inv_half);
-            const float phi = sun[2 * is], th = sun[2 * is + 1];
-            float sphi, cphi, sth, cth;
-            sincosf(phi, &sphi, &cphi);
-            sincosf(th, &sth, &cth);
+            // sun angles through the hardware sine and cosine (argument in revolutions)
+            constexpr float kRev = 0.15915494309189535f;   // 1 / (2 pi)
+            const float phi = sun[2 * is] * kRev, th = sun[2 * is + 1] * kRev;
+            const float sphi = __builtin_amdgcn_sinf(phi), cphi = __builtin_amdgcn_cosf(phi);
+            const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 feature_chunk(ph, cphi, sphi, sth, cth, ks, lane >> 4, fa[rt][ks]);
