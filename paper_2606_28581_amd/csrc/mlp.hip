@@ -103,7 +103,7 @@ struct MlpLds {
     u16 W3[kMlpWidth * kMlpWidth];
     float w4[kMlpWidth];
     float b[3 * kMlpWidth + 1];
-    u16 H[kMlpWaves][2][kPtsPerWave * kHStride];
+    u16 H[kMlpWaves][kPtsPerWave * kHStride];   // one activation tile per wave
 };
 
 __device__ __forceinline__ void load_weights(MlpLds &L, const u16 *wb, const float *wf)
@@ -179,7 +179,7 @@ __device__ __forceinline__ void save_tile(const u16 *Ht, u16 *dst, int64_t base,
 // (every surfel under every sun), or pts[i] and sun[i] when G == 0.  When `saveF` /
 // `saveH` are given the bf16 features [M,128] and hidden activations [3][M,64] are
 // written for the backward.
-__global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(
+__global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_mlp_forward(
     const u16 *__restrict__ wb, const float *__restrict__ wf, const float *__restrict__ pts,
     const float *__restrict__ sun, int64_t M, int64_t G, MlpNorm nz, int prob,
     float *__restrict__ out, u16 *__restrict__ saveF, u16 *__restrict__ saveH)
@@ -189,7 +189,9 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u16 *H0 = L.H[wave][0], *H1 = L.H[wave][1];
+    // each layer reads all of its input fragments from the tile before it writes its
+    // output there (LDS operations of a wave take effect in issue order)
+    u16 *H0 = L.H[wave], *H1 = L.H[wave];
     const int64_t ntile = (M + kPtsPerWave - 1) / kPtsPerWave;
     for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
          tile += (int64_t)gridDim.x * kMlpWaves) {
