@@ -48,6 +48,12 @@ __device__ __forceinline__ f32x4 mfma(const Frag &a, const Frag &b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, c, 0, 0, 0);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __builtin_amdgcn_update_dpp(0.f, v, CTRL, 0xF, 0xF, true);
+}
+
 // --------------------------------------------------------------- weight prep
 // FP32 master -> BF16 copies (W1, W2, W3, w4) and FP32 biases, in the MLP workspace.
 __global__ void k_mlp_prep(const float *__restrict__ w, u16 *__restrict__ wb, float *__restrict__ wf)
@@ -137,20 +143,30 @@ __device__ __forceinline__ void layer_mfma(const Frag (&a)[2][KSTEPS], const u16
     }
 }
 
-// bias + ReLU + bf16 of the accumulator tile into the per-wave LDS tile H [32][kHStride]
-__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[2][4], const float *bias, u16 *H,
-                                             int lane)
+// The accumulator tiles start at the layer's bias (each lane's values of a tile share
+// one output column j = 16 ct + lane % 16), so the MFMA sums land on top of it.
+__device__ __forceinline__ void init_bias(f32x4 (&acc)[2][4], const float *bias, int lane)
+{
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const float bj = bias[ct * 16 + (lane & 15)];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) acc[rt][ct] = f32x4{bj, bj, bj, bj};
+    }
+}
+
+// ReLU + bf16 of the accumulator tile into the per-wave LDS tile H [32][kHStride]
+__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[2][4], u16 *H, int lane)
 {
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
             const int j = ct * 16 + (lane & 15);
-            const float bj = bias[j];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int pt = rt * 16 + 4 * (lane >> 4) + r;
-                H[pt * kHStride + j] = f2bf(fmaxf(acc[rt][ct][r] + bj, 0.f));
+                H[pt * kHStride + j] = f2bf(fmaxf(acc[rt][ct][r], 0.f));
             }
         }
 }
@@ -231,56 +247,56 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
         f32x4 acc[2][4];
         Frag ha[2][2];
         // ---- layer 1 -> H0
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        init_bias(acc, L.b, lane);
         layer_mfma<4>(fa, L.W1, kMlpIn, lane, acc);
-        store_hidden(acc, L.b, H0, lane);
+        store_hidden(acc, H0, lane);
         __builtin_amdgcn_wave_barrier();
         if (saveH) save_tile(H0, saveH, base, M, lane);
         // ---- layer 2: H0 -> H1
         load_hidden(H0, lane, ha);
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        init_bias(acc, L.b + kMlpWidth, lane);
         layer_mfma<2>(ha, L.W2, kMlpWidth, lane, acc);
-        store_hidden(acc, L.b + kMlpWidth, H1, lane);
+        store_hidden(acc, H1, lane);
         __builtin_amdgcn_wave_barrier();
         if (saveH) save_tile(H1, saveH + M * kMlpWidth, base, M, lane);
         // ---- layer 3: H1 -> H0
         load_hidden(H1, lane, ha);
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+        init_bias(acc, L.b + 2 * kMlpWidth, lane);
         layer_mfma<2>(ha, L.W3, kMlpWidth, lane, acc);
         __builtin_amdgcn_wave_barrier();
-        store_hidden(acc, L.b + 2 * kMlpWidth, H0, lane);
-        __builtin_amdgcn_wave_barrier();
-        if (saveH) save_tile(H0, saveH + 2 * M * kMlpWidth, base, M, lane);
-        // ---- output: logit = w4 . h3 + b4 (FP32); 16 lanes share 4 points per tile
+        if (saveH) {
+            store_hidden(acc, H0, lane);
+            __builtin_amdgcn_wave_barrier();
+            save_tile(H0, saveH + 2 * M * kMlpWidth, base, M, lane);
+        }
+        // ---- output: logit = w4 . h3 + b4 (FP32) from the layer-3 accumulators (h3 =
+        // bf16(ReLU)); lane l holds points 16 rt + 4 (l / 16) + r of neurons 16 ct + l % 16,
+        // so each 16-lane row sums its 4 points' partial dot products
         float part[2][4];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int pt = rt * 16 + 4 * (lane >> 4) + r;
-                float s = 0.f;
+            for (int r = 0; r < 4; ++r) part[rt][r] = 0.f;
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
-                    const int j = ct * 16 + (lane & 15);
-                    s = __fmaf_rn(L.w4[j], bf2f(H0[pt * kHStride + j]), s);
-                }
-                part[rt][r] = s;
-            }
+        for (int ct = 0; ct < 4; ++ct) {
+            const float wj = L.w4[ct * 16 + (lane & 15)];
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    part[rt][r] = __fmaf_rn(wj, bf2f(f2bf(fmaxf(acc[rt][ct][r], 0.f))), part[rt][r]);
+        }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int d = 1; d < 16; d <<= 1) part[rt][r] += __shfl_xor(part[rt][r], d, 64);
+            for (int r = 0; r < 4; ++r) {
+                float x = part[rt][r];
+                x += dpp_f<0x140>(x);   // row mirror
+                x += dpp_f<0x141>(x);   // half-row mirror
+                x += dpp_f<0x4E>(x);    // quad_perm [2,3,0,1]
+                x += dpp_f<0xB1>(x);    // quad_perm [1,0,3,2]: every lane of the row has the sum
+                part[rt][r] = x;
+            }
         if ((lane & 15) == 0) {
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
