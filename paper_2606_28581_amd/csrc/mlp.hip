@@ -103,22 +103,41 @@ __device__ __forceinline__ void feature_chunk(const float ph[3], float cphi, flo
     }
 }
 
+// Forward, transposed: every layer computes C^T = W X^T (rows = neurons, columns =
+// points), so lane l of an accumulator tile holds neurons 4 (l / 16) + 0..3 of point
+// l % 16 - four consecutive neurons of one point.  The next layer's B operand needs 8
+// consecutive inputs of one point per lane; numbering that layer's inputs so that its
+// k-step ks, lane group q, element e is neuron 16 (2 ks + e / 4) + 4 q + e % 4 (the
+// columns of W2 and W3 are permuted once when they are copied to LDS) makes those 8 the
+// lane's own accumulator values of tiles 2 ks and 2 ks + 1.  Hidden activations never
+// leave registers.  Features are computed directly in the B layout (point l % 16,
+// features 32 ks + 8 (l / 16) .. + 7), as for the first layer.
 struct MlpLds {
     u16 W1[kMlpWidth * kMlpIn];
-    u16 W2[kMlpWidth * kMlpWidth];
+    u16 W2[kMlpWidth * kMlpWidth];   // columns permuted (see above)
     u16 W3[kMlpWidth * kMlpWidth];
     float w4[kMlpWidth];
     float b[3 * kMlpWidth + 1];
-    u16 H[kMlpWaves][kPtsPerWave * kHStride];   // one activation tile per wave
 };
+
+// input index k of a hidden layer -> neuron of the previous layer
+__device__ __forceinline__ int hidden_input(int k)
+{
+    const int ks = k >> 5, q = (k >> 3) & 3, e = k & 7;
+    return 16 * (2 * ks + (e >> 2)) + 4 * q + (e & 3);
+}
 
 __device__ __forceinline__ void load_weights(MlpLds &L, const u16 *wb, const float *wf)
 {
     const uint4 *src = reinterpret_cast<const uint4 *>(wb);
     uint4 *d1 = reinterpret_cast<uint4 *>(L.W1);
-    for (int i = threadIdx.x; i < (kMlpW1 + kMlpW2 + kMlpW3) / 8; i += blockDim.x) {
-        // W1, W2, W3 are contiguous in both the workspace and the LDS struct
-        d1[i] = src[i];
+    for (int i = threadIdx.x; i < kMlpW1 / 8; i += blockDim.x) d1[i] = src[i];
+    const u16 *w2 = wb + kMlpW1, *w3 = wb + kMlpW1 + kMlpW2;
+    for (int i = threadIdx.x; i < kMlpW2; i += blockDim.x) {
+        const int o = i / kMlpWidth, k = i % kMlpWidth;
+        const int j = o * kMlpWidth + hidden_input(k);
+        L.W2[i] = w2[j];
+        L.W3[i] = w3[j];
     }
     for (int i = threadIdx.x; i < kMlpWidth; i += blockDim.x)
         L.w4[i] = bf2f(wb[kMlpW1 + kMlpW2 + kMlpW3 + i]);
@@ -143,52 +162,59 @@ __device__ __forceinline__ void layer_mfma(const Frag (&a)[2][KSTEPS], const u16
     }
 }
 
-// The accumulator tiles start at the layer's bias (each lane's values of a tile share
-// one output column j = 16 ct + lane % 16), so the MFMA sums land on top of it.
-__device__ __forceinline__ void init_bias(f32x4 (&acc)[2][4], const float *bias, int lane)
+// One layer, transposed: acc[ot][pt] (neurons 16 ot.., points 16 pt..) = bias +
+// W[ot rows] x[pt] over KSTEPS k-steps; W row-major [out][in] (in LDS).
+template <int KSTEPS>
+__device__ __forceinline__ void layer_t(const u16 *W, int ldw, const float *bias,
+                                        const Frag (&x)[2][KSTEPS], int lane, f32x4 (&acc)[4][2])
 {
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const float bj = bias[ct * 16 + (lane & 15)];
+    for (int ot = 0; ot < 4; ++ot) {
+        const float *bo = bias + ot * 16 + 4 * (lane >> 4);
+        const f32x4 b0 = f32x4{bo[0], bo[1], bo[2], bo[3]};
+        acc[ot][0] = b0;
+        acc[ot][1] = b0;
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) acc[rt][ct] = f32x4{bj, bj, bj, bj};
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            Frag w;
+            w.q = *reinterpret_cast<const uint4 *>(W + (ot * 16 + (lane & 15)) * ldw + ks * 32 +
+                                                   8 * (lane >> 4));
+#pragma unroll
+            for (int pt = 0; pt < 2; ++pt) acc[ot][pt] = mfma(w, x[pt][ks], acc[ot][pt]);
+        }
     }
 }
 
-// ReLU + bf16 of the accumulator tile into the per-wave LDS tile H [32][kHStride]
-__device__ __forceinline__ void store_hidden(const f32x4 (&acc)[2][4], u16 *H, int lane)
+// ReLU + bf16 of a layer's accumulators into the next layer's B operands
+__device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][2], Frag (&h)[2][2])
 {
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const int j = ct * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int pt = rt * 16 + 4 * (lane >> 4) + r;
-                H[pt * kHStride + j] = f2bf(fmaxf(acc[rt][ct][r], 0.f));
-            }
-        }
-}
-
-__device__ __forceinline__ void load_hidden(const u16 *H, int lane, Frag (&a)[2][2])
-{
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int pt = 0; pt < 2; ++pt)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
-            a[rt][ks].q = *reinterpret_cast<const uint4 *>(H + (rt * 16 + (lane & 15)) * kHStride +
-                                                          ks * 32 + 8 * (lane >> 4));
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[pt][ks].h[e] = f2bf(fmaxf(acc[2 * ks + (e >> 2)][pt][e & 3], 0.f));
 }
 
-__device__ __forceinline__ void save_tile(const u16 *Ht, u16 *dst, int64_t base, int64_t M, int lane)
+// the activations of one layer for the backward, [M][64] in neuron order: 4 consecutive
+// neurons (8 bytes) per lane and accumulator tile
+__device__ __forceinline__ void save_layer(const Frag (&h)[2][2], u16 *dst, int64_t base, int64_t M,
+                                           int lane)
 {
-    const int row = lane >> 1, half = lane & 1;
-    if (base + row >= M) return;
-    const uint4 *s4 = reinterpret_cast<const uint4 *>(Ht + row * kHStride + half * 32);
-    uint4 *d4 = reinterpret_cast<uint4 *>(dst + (base + row) * kMlpWidth + half * 32);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) d4[q] = s4[q];
+    for (int pt = 0; pt < 2; ++pt) {
+        const int64_t i = base + pt * 16 + (lane & 15);
+        if (i >= M) continue;
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            const Frag &f = h[pt][ot >> 1];
+            const int e0 = 4 * (ot & 1);
+            uint2 v;
+            v.x = (uint32_t)f.h[e0] | ((uint32_t)f.h[e0 + 1] << 16);
+            v.y = (uint32_t)f.h[e0 + 2] | ((uint32_t)f.h[e0 + 3] << 16);
+            *reinterpret_cast<uint2 *>(dst + i * kMlpWidth + ot * 16 + 4 * (lane >> 4)) = v;
+        }
+    }
 }
 
 // Forward over M points.  Point i uses position pts[i % G] and sun[i / G] when G > 0
@@ -205,20 +231,20 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // each layer reads all of its input fragments from the tile before it writes its
-    // output there (LDS operations of a wave take effect in issue order)
-    u16 *H0 = L.H[wave], *H1 = L.H[wave];
     const int64_t ntile = (M + kPtsPerWave - 1) / kPtsPerWave;
     for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
          tile += (int64_t)gridDim.x * kMlpWaves) {
+        // weight fragments are read from LDS per tile (held across tiles they would take
+        // 128 VGPRs)
+        asm volatile("" ::: "memory");
         const int64_t base = tile * kPtsPerWave;
         // all-pairs mode: one division per tile; lanes carry into the next sun
         const int64_t is0 = G > 0 ? base / G : 0, ip0 = base - is0 * G;
-        // ---- features in operand layout
+        // ---- features in the B layout
         Frag fa[2][4];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-            int64_t i = base + rt * 16 + (lane & 15);
+        for (int pt = 0; pt < 2; ++pt) {
+            int64_t i = base + pt * 16 + (lane & 15);
             const bool valid = i < M;
             if (!valid) i = M - 1;
             int64_t ip = i, is = i;
@@ -238,78 +264,49 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
             const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                feature_chunk(ph, cphi, sphi, sth, cth, ks, lane >> 4, fa[rt][ks]);
+                feature_chunk(ph, cphi, sphi, sth, cth, ks, lane >> 4, fa[pt][ks]);
                 if (saveF && valid)
                     *reinterpret_cast<uint4 *>(saveF + i * kMlpIn + ks * 32 + 8 * (lane >> 4)) =
-                        fa[rt][ks].q;
+                        fa[pt][ks].q;
             }
         }
-        f32x4 acc[2][4];
-        Frag ha[2][2];
-        // ---- layer 1 -> H0
-        init_bias(acc, L.b, lane);
-        layer_mfma<4>(fa, L.W1, kMlpIn, lane, acc);
-        store_hidden(acc, H0, lane);
-        __builtin_amdgcn_wave_barrier();
-        if (saveH) save_tile(H0, saveH, base, M, lane);
-        // ---- layer 2: H0 -> H1
-        load_hidden(H0, lane, ha);
-        init_bias(acc, L.b + kMlpWidth, lane);
-        layer_mfma<2>(ha, L.W2, kMlpWidth, lane, acc);
-        store_hidden(acc, H1, lane);
-        __builtin_amdgcn_wave_barrier();
-        if (saveH) save_tile(H1, saveH + M * kMlpWidth, base, M, lane);
-        // ---- layer 3: H1 -> H0
-        load_hidden(H1, lane, ha);
-        init_bias(acc, L.b + 2 * kMlpWidth, lane);
-        layer_mfma<2>(ha, L.W3, kMlpWidth, lane, acc);
-        __builtin_amdgcn_wave_barrier();
-        if (saveH) {
-            store_hidden(acc, H0, lane);
-            __builtin_amdgcn_wave_barrier();
-            save_tile(H0, saveH + 2 * M * kMlpWidth, base, M, lane);
-        }
-        // ---- output: logit = w4 . h3 + b4 (FP32) from the layer-3 accumulators (h3 =
-        // bf16(ReLU)); lane l holds points 16 rt + 4 (l / 16) + r of neurons 16 ct + l % 16,
-        // so each 16-lane row sums its 4 points' partial dot products
-        float part[2][4];
+        f32x4 acc[4][2];
+        Frag h[2][2];
+        layer_t<4>(L.W1, kMlpIn, L.b, fa, lane, acc);
+        relu_to_operand(acc, h);
+        if (saveH) save_layer(h, saveH, base, M, lane);
+        layer_t<2>(L.W2, kMlpWidth, L.b + kMlpWidth, h, lane, acc);
+        relu_to_operand(acc, h);
+        if (saveH) save_layer(h, saveH + M * kMlpWidth, base, M, lane);
+        layer_t<2>(L.W3, kMlpWidth, L.b + 2 * kMlpWidth, h, lane, acc);
+        relu_to_operand(acc, h);
+        if (saveH) save_layer(h, saveH + 2 * M * kMlpWidth, base, M, lane);
+        // ---- output: logit = w4 . h3 + b4 (FP32); lane (q, n) holds neurons
+        // 16 ot + 4 q + 0..3 of point n, so the 4 lane groups of a column are summed
+        float part[2];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
+        for (int pt = 0; pt < 2; ++pt) {
+            float s = 0.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) part[rt][r] = 0.f;
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-            const float wj = L.w4[ct * 16 + (lane & 15)];
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+            for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    part[rt][r] = __fmaf_rn(wj, bf2f(f2bf(fmaxf(acc[rt][ct][r], 0.f))), part[rt][r]);
+                    s = __fmaf_rn(L.w4[ot * 16 + 4 * (lane >> 4) + r],
+                                  bf2f(h[pt][ot >> 1].h[4 * (ot & 1) + r]), s);
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            part[pt] = s;
         }
+        if (lane < 16) {
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float x = part[rt][r];
-                x += dpp_f<0x140>(x);   // row mirror
-                x += dpp_f<0x141>(x);   // half-row mirror
-                x += dpp_f<0x4E>(x);    // quad_perm [2,3,0,1]
-                x += dpp_f<0xB1>(x);    // quad_perm [1,0,3,2]: every lane of the row has the sum
-                part[rt][r] = x;
-            }
-        if ((lane & 15) == 0) {
-#pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = base + rt * 16 + 4 * (lane >> 4) + r;
-                    if (i < M) {
-                        const float lg = part[rt][r] + L.b[3 * kMlpWidth];
-                        out[i] = prob ? 1.f / (1.f + expf(-lg)) : lg;
-                    }
+            for (int pt = 0; pt < 2; ++pt) {
+                const int64_t i = base + pt * 16 + lane;
+                if (i < M) {
+                    const float lg = part[pt] + L.b[3 * kMlpWidth];
+                    out[i] = prob ? 1.f / (1.f + expf(-lg)) : lg;
                 }
+            }
         }
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
