@@ -493,6 +493,9 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     int lastpos = 0, ncontrib = 0, neval = 0;
     bool done = !inside;
     const int B = min(rc.batch, NT);
+    // LDS stride between a record's float4 groups: a compile-time constant (>= every
+    // batch) so that the group reads are immediate offsets from one address
+    constexpr int BS = NT < 256 ? NT : 256;
     float4 q0, q1, q2, q3, q4, q5;
 #define SS_FETCH_FWD(BASE, CNT)                                                        \
     if (tid < (CNT)) {                                                                 \
@@ -509,8 +512,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
         const int nb = (int)min((uint32_t)B, end - b0);
         __syncthreads();
         if (tid < nb) {
-            lds[tid] = q0; lds[B + tid] = q1; lds[2 * B + tid] = q2; lds[3 * B + tid] = q3;
-            if (!DEPTH_ONLY) { lds[4 * B + tid] = q4; lds[5 * B + tid] = q5; }
+            lds[tid] = q0; lds[BS + tid] = q1; lds[2 * BS + tid] = q2; lds[3 * BS + tid] = q3;
+            if (!DEPTH_ONLY) { lds[4 * BS + tid] = q4; lds[5 * BS + tid] = q5; }
         }
         __syncthreads();
         const uint32_t b1 = b0 + B;
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
             while (m != 0) {
                 const int jc = c0 + (int)__builtin_ctzll(m);
                 m &= m - 1;
-                const float4 r0 = lds[jc], r1 = lds[B + jc], r2 = lds[2 * B + jc], r3 = lds[3 * B + jc];
+                const float4 r0 = lds[jc], r1 = lds[BS + jc], r2 = lds[2 * BS + jc], r3 = lds[3 * BS + jc];
                 ++neval;
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
                 // branch-free: a skipped pair accumulates with weight 0 (w * x + a == a
@@ -539,7 +542,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                 const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
                 aD = __fmaf_rn(w, z, aD);
                 if (!DEPTH_ONLY) {
-                    const float4 r4 = lds[4 * B + jc], r5 = lds[5 * B + jc];
+                    const float4 r4 = lds[4 * BS + jc], r5 = lds[5 * BS + jc];
                     a0 = __fmaf_rn(w, r4.x, a0);
                     a1 = __fmaf_rn(w, r4.y, a1);
                     a2 = __fmaf_rn(w, r4.z, a2);
@@ -639,7 +642,9 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
-    const size_t lds = (size_t)min(rc.batch, ts * ts) * kRecVec4 * sizeof(float4);
+    // records staged at a fixed stride of min(ts^2, 256) float4 per field group; the
+    // depth-only pass stages the first 4 of a record's 6 groups
+    const size_t lds = (size_t)min(ts * ts, 256) * (depth_only ? 4 : kRecVec4) * sizeof(float4);
 #define SS_FWD(TS_)                                                                              \
     if (ts == TS_) {                                                                             \
         if (depth_only)                                                                          \
