@@ -26,7 +26,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# FP32 vector peak without packed dual-FP32 issue (disabled in this build):
+# FP32 vector peak without packed dual-FP32 issue (the library is compiled with packed
+# FP32 operations disabled):
 # 256 CU x 64 FMA lanes/clk x 2 flop x 2.4 GHz.
 VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 # Algorithmic FP32 flops per contributing (pixel, surfel) pair (FMA = 2, exp = 4):
@@ -259,7 +260,7 @@ def training_scale(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (over "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 (over "
                                    "several GPUs the path would shard views and all-reduce the "
                                    "surfel gradients once per step)"}))
         sys.exit(2)
