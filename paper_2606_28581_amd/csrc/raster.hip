@@ -553,10 +553,16 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                 }
                 if (CM) cmc |= take ? 1ull << (jc - c0) : 0ull;
                 Tr = take ? Tn : Tr;
-                lastpos = take ? pos0 + jc + 1 : lastpos;
-                ncontrib += take ? 1 : 0;
+                if (!CM) {   // with contributor masks both follow from cmc once per chunk
+                    lastpos = take ? pos0 + jc + 1 : lastpos;
+                    ncontrib += take ? 1 : 0;
+                }
                 done = done || stop;
                 m = stop ? 0ull : m;
+            }
+            if (CM && cmc != 0ull) {
+                lastpos = pos0 + c0 + 64 - (int)__builtin_clzll(cmc);
+                ncontrib += (int)__popcll(cmc);
             }
             if (CM && cmask) {
                 const int P0 = pos0 + c0, w = P0 >> 6;
