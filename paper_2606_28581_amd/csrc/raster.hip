@@ -403,7 +403,8 @@ __device__ __forceinline__ PairEval eval_pair(const float4 r0, const float4 r1, 
     const float rho = e.ub ? ru : rf;
     e.G = ex2(__fmul_rn(rho, kNegHalfLog2e));
     e.oG = __fmul_rn(r3.x, e.G);
-    e.alpha = fminf(rc.alpha_max, e.oG);
+    // min(alpha_max, oG) for oG >= 0, in one median-of-three instruction
+    e.alpha = __builtin_amdgcn_fmed3f(e.oG, 0.f, rc.alpha_max);
     return e;
 }
 
@@ -1046,7 +1047,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 const int jl = act ? 63 - (int)__builtin_clzll(m) : 0;
                 const int j = c0 + jl;
                 if (act) m &= ~(1ull << jl);
-                const float4 *R = lds + j * kRecVec4;
+                const float4 *R = lds + __mul24(j, kRecVec4);   // j < 256: 24-bit multiply
                 const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
                 // branch-free: every lane evaluates the row's record; lanes that do not
                 // contribute (outside [0, last) or alpha < alpha_min) get zero gradients
