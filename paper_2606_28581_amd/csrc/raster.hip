@@ -870,15 +870,17 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
                                                float two_is2, float alpha_max, float &Tr,
                                                float &gS, float (&gr)[16])
 {
+    // gradient arithmetic with explicit fused multiply-adds (the discrete decisions -
+    // contrib, ub, unclamped - come from eval_pair and the forward's own tests)
     const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
     const float Tb = Tr * rom;
     const float w = contrib ? e.alpha * Tb : 0.f;
     const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
-    float gf = pa.gA0 * r4.x + pa.gA1 * r4.y + pa.gA2 * r4.z + pa.gD * z + pa.gN0 * r5.x +
-               pa.gN1 * r5.y + pa.gN2 * r5.z;
-    if (has_vis) gf += pa.gV * r4.w;
-    const float dal = contrib ? Tb * gf - gS * rom : 0.f;
-    gS += w * gf;
+    float gf = fmaf(pa.gA0, r4.x, fmaf(pa.gA1, r4.y, fmaf(pa.gA2, r4.z, fmaf(pa.gD, z,
+               fmaf(pa.gN0, r5.x, fmaf(pa.gN1, r5.y, pa.gN2 * r5.z))))));
+    if (has_vis) gf = fmaf(pa.gV, r4.w, gf);
+    const float dal = contrib ? fmaf(Tb, gf, -gS * rom) : 0.f;
+    gS = fmaf(w, gf, gS);
     Tr = contrib ? Tb : Tr;
     const float dz = w * pa.gD;
     gr[G_AR] = w * pa.gA0; gr[G_AG] = w * pa.gA1; gr[G_AB] = w * pa.gA2;
@@ -888,16 +890,18 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
     gr[G_O] = unclamped ? e.G * dal : 0.f;
     const float dG = unclamped ? r3.x * dal : 0.f;
     const float drho = -0.5f * e.G * dG;
-    const float du0 = 2.f * e.u0 * drho - r3.z * dz;
-    const float du1 = 2.f * e.u1 * drho - r3.w * dz;
+    const float drho2 = drho + drho;
+    const float du0 = fmaf(e.u0, drho2, -r3.z * dz);
+    const float du1 = fmaf(e.u1, drho2, -r3.w * dz);
     gr[G_KU] = e.ub ? -e.u0 * dz : 0.f;
     gr[G_KV] = e.ub ? -e.u1 * dz : 0.f;
     gr[G_Q00] = e.ub ? du0 * e.dx : 0.f;
     gr[G_Q01] = e.ub ? du0 * e.dy : 0.f;
     gr[G_Q10] = e.ub ? du1 * e.dx : 0.f;
     gr[G_Q11] = e.ub ? du1 * e.dy : 0.f;
-    const float ddx = e.ub ? r2.x * du0 + r2.z * du1 : two_is2 * e.dx * drho;
-    const float ddy = e.ub ? r2.y * du0 + r2.w * du1 : two_is2 * e.dy * drho;
+    const float fdrho = two_is2 * drho;
+    const float ddx = e.ub ? fmaf(r2.x, du0, r2.z * du1) : e.dx * fdrho;
+    const float ddy = e.ub ? fmaf(r2.y, du0, r2.w * du1) : e.dy * fdrho;
     gr[G_CX] = -ddx;
     gr[G_CY] = -ddy;
 }
