@@ -201,7 +201,8 @@ ss_status ss_shadow_plain(ss_plan *plan, const ss_surfels *s, const ss_views *v,
  *   tile_ranges [n_tiles,2]   uint32 [start,end) into tile_lists, n_tiles over all
  *                             views in view order, row-major tiles inside a view
  *   tile_lists  [pairs]       uint32 surfel indices (pairs = *n_pairs)
- *   records     [n_views,n,24] float projected-surfel records, or NULL
+ *   records     [n_views,n,24] float projected-surfel records, or NULL (the shadow
+ *                             pass keeps only floats 0..15; 16..23 read as zero)
  * *n_tiles and *n_pairs (host) receive the sizes; any output pointer may be NULL. */
 ss_status ss_debug_binning(ss_plan *plan, int32_t which, uint32_t *order,
                            int32_t *surf_tiles, uint32_t *tile_ranges,

@@ -182,7 +182,7 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.sorted_main = take(n * 16 * 4);
     L.sk_a = take(n * 4); L.sk_b = take(n * 4); L.sv_a = take(n * 4); L.sv_b = take(n * 4);
     L.sorted_sun = take(n * 16 * 4);
-    L.rec_main = take(vn * kRecFloats * 4);
+    L.rec_main = take(vn * kRecStride4 * 16);
     L.tiles_main = take(vn * sizeof(short4));
     L.counts_main = take(vn * 4);
     L.offs_main = take((vn + 1) * 4);
@@ -193,7 +193,7 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     L.recgrad = take(vn * kGradFloats * 4);
     L.colour_parts = take((size_t)p->tiles_main_max * 16 * 4);
     L.dF_parts = take((size_t)project_bwd_blocks(p->n) * nv * 8 * 4);
-    L.rec_sun = take(vn * kRecFloats * 4);
+    L.rec_sun = take(vn * kSunRecStride4 * 16);
     L.tiles_sun = take(vn * sizeof(short4));
     L.counts_sun = take(vn * 4);
     L.offs_sun = take((vn + 1) * 4);
@@ -737,7 +737,8 @@ ss_status ss_debug_binning(ss_plan *p, int32_t which, uint32_t *order, int32_t *
                                   st));
     if (records && p->n > 0)
         SS_HIP(launch_unpermute_rows(ord, p->n, p->nv, p->at<uint32_t>(sun ? L.rec_sun : L.rec_main),
-                                     kRecFloats, reinterpret_cast<uint32_t *>(records), st));
+                                     4 * (sun ? kSunRecStride4 : kRecStride4), kRecFloats,
+                                     reinterpret_cast<uint32_t *>(records), st));
     SS_HIP(hipStreamSynchronize(st));
     return SS_OK;
 }

@@ -237,8 +237,18 @@ __global__ __launch_bounds__(256) void k_project(
     R[5] = make_float4((float)(s * m[0]), (float)(s * m[1]), (float)(s * m[2]), (float)nsign);
     __syncthreads();
     const int64_t nrec = min((int64_t)blockDim.x, n - r0);
-    float4 *dst = rec + ((size_t)v * (size_t)n + (size_t)r0) * kRecVec4;
-    for (int i = threadIdx.x; i < nrec * kRecVec4; i += blockDim.x) dst[i] = srec[i];
+    // whole slots, so every written line is written in full
+    if (sun) {
+        float4 *dst = rec + ((size_t)v * (size_t)n + (size_t)r0) * kSunRecStride4;
+        for (int i = threadIdx.x; i < nrec * kSunRecStride4; i += blockDim.x)
+            dst[i] = srec[(i >> 2) * kRecVec4 + (i & 3)];
+    } else {
+        float4 *dst = rec + ((size_t)v * (size_t)n + (size_t)r0) * kRecStride4;
+        for (int i = threadIdx.x; i < nrec * kRecStride4; i += blockDim.x) {
+            const int k = i & 7;
+            dst[i] = k < kRecVec4 ? srec[(i >> 3) * kRecVec4 + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
 }
 
 hipError_t launch_project(const float *sorted, int64_t n, int32_t nv, const ViewDesc *views,
@@ -489,7 +499,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     const bool inside = px < vd.W && py < vd.H;
     const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
     const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-    const float4 *recv = rec + (size_t)v * (size_t)n * kRecVec4;
+    constexpr int RS = DEPTH_ONLY ? kSunRecStride4 : kRecStride4;   // record slot
+    const float4 *recv = rec + (size_t)v * (size_t)n * RS;
     float Tr = 1.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, aV = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
     int lastpos = 0, ncontrib = 0, neval = 0;
     bool done = !inside;
@@ -501,7 +512,7 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
 #define SS_FETCH_FWD(BASE, CNT)                                                        \
     if (tid < (CNT)) {                                                                 \
         const uint32_t idx_ = min(lists[(BASE) + tid], (uint32_t)(n - 1));             \
-        const float4 *src_ = recv + (size_t)idx_ * kRecVec4;                           \
+        const float4 *src_ = recv + (size_t)idx_ * RS;                           \
         q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3];                        \
         if (!DEPTH_ONLY) { q4 = src_[4]; q5 = src_[5]; }                               \
     }
@@ -976,7 +987,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
 
     const uint32_t start = ranges[2 * tile];
     const int tile_len = (int)(ranges[2 * tile + 1] - start);
-    const float4 *recv = rec + (size_t)v * (size_t)n * kRecVec4;
+    const float4 *recv = rec + (size_t)v * (size_t)n * kRecStride4;
     float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
     float gS = 0.f;
     const int batch = min(rc.batch, NT);
@@ -991,7 +1002,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
 #define SS_FETCH_BWD(BB, CNT)                                                          \
     if (tid < (CNT)) {                                                                 \
         qidx = min(lists[start + (BB) + tid], (uint32_t)(n - 1));                      \
-        const float4 *src_ = recv + (size_t)qidx * kRecVec4;                           \
+        const float4 *src_ = recv + (size_t)qidx * kRecStride4;                           \
         q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3]; q4 = src_[4]; q5 = src_[5]; \
     }
     // batches on the forward's grid ([k * batch, (k + 1) * batch) from the list start),
@@ -1325,25 +1336,25 @@ hipError_t launch_dF_reduce(const float *partials, int nblocks, int32_t nv, floa
 
 // Scatter per-(view, rank) rows back to per-(view, surfel) order for debug output.
 __global__ void k_unpermute_rows(const uint32_t *__restrict__ order, int64_t n, int32_t nv,
-                                 const uint32_t *__restrict__ in, int row_words,
-                                 uint32_t *__restrict__ out)
+                                 const uint32_t *__restrict__ in, int in_stride,
+                                 int row_words, uint32_t *__restrict__ out)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     if (r >= n) return;
     if (order[r] >= n) return;
-    const int64_t src = ((int64_t)v * n + r) * row_words;
+    const int64_t src = ((int64_t)v * n + r) * in_stride;
     const int64_t dst = ((int64_t)v * n + order[r]) * row_words;
-    for (int k = 0; k < row_words; ++k) out[dst + k] = in[src + k];
+    for (int k = 0; k < row_words; ++k) out[dst + k] = k < in_stride ? in[src + k] : 0u;
 }
 
 hipError_t launch_unpermute_rows(const uint32_t *order, int64_t n, int32_t nv,
-                                 const uint32_t *in, int row_words, uint32_t *out,
-                                 hipStream_t st)
+                                 const uint32_t *in, int in_stride, int row_words,
+                                 uint32_t *out, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_unpermute_rows, dim3((unsigned)((n + 255) / 256), (unsigned)nv),
-                       dim3(256), 0, st, order, n, nv, in, row_words, out);
+                       dim3(256), 0, st, order, n, nv, in, in_stride, row_words, out);
     return hipGetLastError();
 }
 

@@ -11,7 +11,11 @@ constexpr int kWave = 64;
 
 // ---------------------------------------------------------------------------------
 // Projected-surfel record: one per (view, depth rank), 24 floats = 96 B = 6 x float4,
-// array-of-structures so an LDS batch load is 6 contiguous float4 per record.
+// array-of-structures so an LDS batch load is 6 contiguous float4 per record.  The raster
+// kernels gather records at random, so each sits in a slot that is one aligned piece of an
+// L2 line (at a 96-byte stride half of them would straddle two lines): view records in
+// 128-byte slots (the last 32 B zero), sun-view records, of which only vec4 0..3 exist, in
+// 64-byte slots.
 //   vec4 0: box_x, box_y, c_hi.x, c_hi.y
 //   vec4 1: c_lo.x, c_lo.y, off_u, off_f
 //   vec4 2: Q00, Q01, Q10, Q11
@@ -28,7 +32,7 @@ constexpr int kWave = 64;
 //   box    : inclusive pixel box as int16 pairs (lo | hi << 16) for per-wave culling
 //   v      : sun visibility composited into the V channel (1 when none is given)
 //   nsign  : +-1, normal orientation (n = nsign * m / |m|, m = t_u x t_v)
-// The depth-only (sun-view) raster reads only vec4 0..3.
+// The depth-only (sun-view) raster reads only vec4 0..3, the only ones sun records hold.
 // Raster work counters (contributing, evaluated pairs): every wave adds to the slot of its
 // tile modulo kStatSlots, each slot on its own 128-byte line, so the adds of 10^6 waves
 // do not queue on one address; readers sum the slots.
@@ -36,6 +40,8 @@ constexpr int kStatSlots = 256;
 constexpr int kStatStride = 16;   // 64-bit words per slot
 constexpr int kRecFloats = 24;
 constexpr int kRecVec4 = 6;
+constexpr int kRecStride4 = 8;      // float4 per view record slot
+constexpr int kSunRecStride4 = 4;   // float4 per sun-view record slot
 
 // Per-(view, surfel) record gradient, 16 floats (written with one 16-lane atomic
 // instruction per wave after a transpose reduction).
@@ -169,9 +175,11 @@ hipError_t launch_project_bwd(const float *sorted, int64_t n, const uint32_t *or
                               hipStream_t st);
 hipError_t launch_dF_reduce(const float *partials, int nblocks, int32_t nv, float *d_dF,
                             hipStream_t st);
+// out row (v, order[r]) = the first row_words words of in row (v, r), in rows in_stride
+// words apart (words past in_stride read as zero)
 hipError_t launch_unpermute_rows(const uint32_t *order, int64_t n, int32_t nv,
-                                 const uint32_t *in, int row_words, uint32_t *out,
-                                 hipStream_t st);
+                                 const uint32_t *in, int in_stride, int row_words,
+                                 uint32_t *out, hipStream_t st);
 hipError_t launch_unpermute_tiles(const uint32_t *order, int64_t n, int32_t nv, const short4 *t,
                                   int32_t *out, hipStream_t st);
 hipError_t launch_map_through(const uint32_t *order, int64_t n_order,
