@@ -37,3 +37,30 @@ def test_sun_cameras_depth_maps_and_visibility(S, ts):
     b = plan.debug_binning(1)
     order = oracle.depth_order(sc["surfels"]["mean"], sc["b_z"])
     np.testing.assert_array_equal(b["order"].astype(np.int64), order)
+
+
+def test_sun_records_centre_box_and_unstored_fields():
+    """Sun-view records: the FP32 hi + lo centre equals the FP64 sun-camera projection and
+    the pixel box equals the FP64 support box; the shadow pass stores only a record's
+    first 16 floats, so the copy-out reads the other 8 as zero."""
+    sc = synth.make_scene(synth.tiny(n_surfels=500, views=((40, 40), (31, 22)), seed=9))
+    S, ts = 100, 8
+    plan, surf, views = make_plan(sc, ts=ts, S=S, with_sun=True)
+    plan.shadow(surf, views)
+    rec = plan.debug_binning(1, records=True)["records"]
+    st = oracle_settings(ts=ts, S=S)
+    for v in range(len(sc["width"])):
+        Bs, bs, _ = oracle.sun_camera(sc, v, S=S)
+        c, _, pix, _ = oracle.binning(sc, Bs, bs, S, S, ts, st)
+        cg = rec[v][:, 2:4].astype(np.float64) + rec[v][:, 4:6].astype(np.float64)
+        np.testing.assert_allclose(cg, c, rtol=1e-12, atol=1e-9)
+        box = rec[v][:, 0:2].view(np.uint32)
+        lo = (box & 0xFFFF).astype(np.uint16).view(np.int16).astype(np.int64)
+        hi = (box >> 16).astype(np.uint16).view(np.int16).astype(np.int64)
+        live = (pix[:, 0] <= pix[:, 1]) & (pix[:, 2] <= pix[:, 3])
+        assert live.sum() > 100
+        np.testing.assert_array_equal(lo[live, 0], pix[live, 0])
+        np.testing.assert_array_equal(hi[live, 0], pix[live, 1])
+        np.testing.assert_array_equal(lo[live, 1], pix[live, 2])
+        np.testing.assert_array_equal(hi[live, 1], pix[live, 3])
+        assert not rec[v][:, 16:].any()
