@@ -122,7 +122,7 @@ hipError_t launch_sun_cameras(const float *mean, int64_t n, int32_t nv, const fl
 __global__ void k_shadow_query(const float *__restrict__ mean, int64_t n,
                                const SunCam *__restrict__ sun, const float *__restrict__ D,
                                int32_t S, float bz, float esm_c, float esm_bias,
-                               float *__restrict__ vis, float band)
+                               float *__restrict__ vis, float band, bool rows16)
 {
     // view-outermost grid: the blocks in flight read one view's sun map, which stays in L2
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,12 +139,35 @@ __global__ void k_shadow_query(const float *__restrict__ mean, int64_t n,
     const float dk = __fsub_rn(bz, (float)p2);
     const float zfar = (float)c.zfar;
     const float *Dv = D + (int64_t)v * S * S;
+    // texels in row-major window order, each row's three read together: with rows16 (S a
+    // multiple of 4 and D 16-byte aligned) every map row is 16-byte aligned, and a window
+    // row inside the map lies in the aligned float4 at its first texel or in that one and
+    // the next
+    const double tx0 = fx - 1;
+    const bool cols_in = tx0 >= 0 && tx0 + 2 < S;
     float acc = 0.f;
-    for (int t = 0; t < 9; ++t) {
-        const double tx = fx + (t % 3) - 1, ty = fy + (t / 3) - 1;
-        float Dt = zfar;
-        if (tx >= 0 && ty >= 0 && tx < S && ty < S) Dt = Dv[(int64_t)ty * S + (int64_t)tx];
-        acc += expf(esm_c * (Dt - dk + esm_bias));
+    for (int r = 0; r < 3; ++r) {
+        const double ty = fy + r - 1;
+        float d[3] = {zfar, zfar, zfar};
+        if (ty >= 0 && ty < S) {
+            const float *row = Dv + (int64_t)ty * S;
+            if (rows16 && cols_in) {
+                const int64_t x0 = (int64_t)tx0, a = x0 & ~(int64_t)3;
+                const int o = (int)(x0 - a);
+                const float4 A = *reinterpret_cast<const float4 *>(row + a);
+                float4 B = A;
+                if (o >= 2) B = *reinterpret_cast<const float4 *>(row + a + 4);
+                d[0] = o == 0 ? A.x : o == 1 ? A.y : o == 2 ? A.z : A.w;
+                d[1] = o == 0 ? A.y : o == 1 ? A.z : o == 2 ? A.w : B.x;
+                d[2] = o == 0 ? A.z : o == 1 ? A.w : o == 2 ? B.x : B.y;
+            } else {
+                for (int i = 0; i < 3; ++i) {
+                    const double tx = tx0 + i;
+                    if (tx >= 0 && tx < S) d[i] = row[(int64_t)tx];
+                }
+            }
+        }
+        for (int i = 0; i < 3; ++i) acc += expf(esm_c * (d[i] - dk + esm_bias));
     }
     acc *= (1.f / 9.f);
     vis[(int64_t)v * n + k] = fminf(1.f, acc);
@@ -155,8 +178,9 @@ hipError_t launch_shadow_query(const float *mean, int64_t n, int32_t nv, const S
                                float esm_bias, float *vis, float band, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    const bool rows16 = S % 4 == 0 && reinterpret_cast<uintptr_t>(sun_depth) % 16 == 0;
     hipLaunchKernelGGL(k_shadow_query, dim3((unsigned)((n + 255) / 256), (unsigned)nv), dim3(256),
-                       0, st, mean, n, sun, sun_depth, S, bz, esm_c, esm_bias, vis, band);
+                       0, st, mean, n, sun, sun_depth, S, bz, esm_c, esm_bias, vis, band, rows16);
     return hipGetLastError();
 }
 
