@@ -240,6 +240,7 @@ static RasterConsts consts(const ss_raster_settings &s)
     rc.T_min = s.T_min;
     const double sig = (double)s.lowpass_sigma;
     rc.inv_s2 = (float)(1.0 / (sig * sig));
+    rc.two_inv_s2 = 2.f * rc.inv_s2;
     rc.lowpass_mode = s.lowpass_mode;
     rc.batch = s.batch_depth;
     rc.esm_c = s.esm_c;

@@ -943,10 +943,12 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
 {
     constexpr int NT = TS * TS;
     constexpr int NW = NT / 64;
+    // LDS: the staged batch (at offset 0, so a record's address is one multiply), its
+    // ranks, the waves' colour sums, the tile's largest `last`
     extern __shared__ float4 lds[];
     uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + min(rc.batch, NT) * kRecVec4);
-    __shared__ float red[NW][16];
-    __shared__ int max_last;
+    float(*red)[16] = reinterpret_cast<float(*)[16]>(lds_idx + min(rc.batch, NT));
+    int &max_last = *reinterpret_cast<int *>(red + NW);
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
     const ViewDesc vd = views[v];
@@ -991,7 +993,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
     float gS = 0.f;
     const int batch = min(rc.batch, NT);
-    const float two_is2 = 2.f * rc.inv_s2;
+    const float two_is2 = rc.two_inv_s2;
     const int blk_last = min(max_last, tile_len);   // a stale `last` cannot read past the list
     // the row walks records up to the largest `last` among its 16 pixels
     const int row_last = row_max(mylast);
@@ -1110,7 +1112,8 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
-    const size_t lds = (size_t)min(rc.batch, ts * ts) * (kRecVec4 * sizeof(float4) + sizeof(uint32_t));
+    const size_t lds = (size_t)min(rc.batch, ts * ts) * (kRecVec4 * sizeof(float4) + sizeof(uint32_t)) +
+                       (size_t)(ts * ts / 64) * 16 * sizeof(float) + sizeof(int);
 #define SS_BWD(TS_)                                                                          \
     if (ts == TS_) {                                                                         \
         if (has_vis)                                                                         \

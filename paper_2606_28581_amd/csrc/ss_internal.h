@@ -71,6 +71,7 @@ struct RasterConsts {
     int32_t lowpass_mode;
     int32_t batch;
     float esm_c, esm_bias;
+    float two_inv_s2;   // 2 inv_s2, a kernel argument so that loops read it from an SGPR
     double alpha_min_d, sigma_d, det_rel_eps_d;
 };
 
