@@ -80,15 +80,21 @@ struct SurfelPtrs {
     int64_t n;
 };
 
-// Workgroups go round-robin to the 8 XCDs, each with its own L2.  Handing every XCD a
-// contiguous run of tiles keeps neighbouring tiles (or the views of one chunk of surfels)
-// under one L2.  Bijective on [0, nblocks).
+// Workgroups go round-robin to the 8 XCDs, each with its own L2, and an XCD never takes
+// another's.  XCD x gets chunks x, x + 8, x + 16, ... of kXcdChunk consecutive ids: the
+// tiles of a few tile rows (or the views of a few blocks of surfels) share one L2, and
+// every XCD samples the whole id range, so work that varies along it (views of different
+// size and density) is spread evenly; one contiguous run per XCD left the busiest XCD
+// 8 % above the mean.  Bijective on [0, nblocks): the last nblocks % (8 kXcdChunk) ids
+// map to themselves.
+constexpr int kXcdChunk = 512;
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 {
     constexpr int kXcd = 8;
-    const int q = nblocks / kXcd, r = nblocks % kXcd;
+    const int full = nblocks - nblocks % (kXcd * kXcdChunk);
+    if (bid >= full) return bid;
     const int x = bid % kXcd, i = bid / kXcd;
-    return x * q + min(x, r) + i;
+    return ((i / kXcdChunk) * kXcd + x) * kXcdChunk + i % kXcdChunk;
 }
 
 // ------------------------------------------------------------------- launchers
