@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_project(
     const uint32_t *__restrict__ tmask)
 {
     // the block's 256 records are staged in LDS and written back as one contiguous run.
-    // Blocks run view-innermost (block = rank block x views + view), in XCD-contiguous
+    // Blocks run view-innermost (block = rank block x views + view), in xcd_tile's chunked
     // order, so the views of one rank block share the surfel parameters in one L2.
     __shared__ float4 srec[256 * kRecVec4];
     const int64_t L = xcd_tile((int)blockIdx.x, (int)gridDim.x);
