@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_table(
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
     const uint32_t *keys, const SegDesc *segs, int nseg, const unsigned long long *n_dev,
-    int64_t cap, int64_t n_host, int shift, int nbits, uint32_t *hist)
+    int64_t cap, int64_t n_host, int shift, uint32_t *hist)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -345,7 +345,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
     if (br.live) {
         const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
         const int64_t wbase = br.lo + (int64_t)w * (kSortItems * kWave);
-        const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
         // all of the wave's keys are loaded before any is counted
         uint32_t key[kSortItems];
 #pragma unroll
@@ -353,13 +352,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
             const int64_t i = wbase + it * kWave + lane;
             key[it] = i < br.hi ? keys[i] : 0u;
         }
+        // one LDS add per key: the LDS serialises lanes that hit the same counter, which
+        // costs less than finding each digit's group of lanes with ballots
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
-            const bool valid = wbase + it * kWave + lane < br.hi;
-            const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
-            // one LDS add per group of lanes with the same digit (its lowest lane)
-            const uint64_t m = digit_peers(d, valid, nbits);
-            if (valid && (m & lt_mask) == 0) atomicAdd(&h[d], (uint32_t)__popcll(m));
+            if (wbase + it * kWave + lane < br.hi)
+                atomicAdd(&h[((key[it] - br.base) >> shift) & 255u], 1u);
         }
     }
     __syncthreads();
@@ -567,7 +565,7 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
         const int shift = 8 * p;
         const int nbits = std::max(1, std::min(8, bits - shift));
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, segs,
-                           nseg, n_dev, cap, n_host, shift, nbits, hist);
+                           nseg, n_dev, cap, n_host, shift, hist);
         hipLaunchKernelGGL(k_hist_scan_reduce, dim3((unsigned)nparts), dim3(kSortThreads), 0,
                            st, hist, hlen, parts);
         hipLaunchKernelGGL(k_hist_scan_partials, dim3(1), dim3(kScanPartialsThreads), 0, st, parts,
