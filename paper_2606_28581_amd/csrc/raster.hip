@@ -487,7 +487,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     // records it composited (the backward walks only those)
     constexpr bool CM = TS == 8 && !DEPTH_ONLY;
     extern __shared__ float4 lds[];
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    // sun maps are equal in size and even in work: one contiguous run of tiles per XCD
+    const int tile = xcd_tile<!DEPTH_ONLY>((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
     const ViewDesc vd = views[v];
     const int lt = tile - vd.tile_off;

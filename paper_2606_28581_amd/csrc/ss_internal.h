@@ -85,12 +85,20 @@ struct SurfelPtrs {
 // tiles of a few tile rows (or the views of a few blocks of surfels) share one L2, and
 // every XCD samples the whole id range, so work that varies along it (views of different
 // size and density) is spread evenly; one contiguous run per XCD left the busiest XCD
-// 8 % above the mean.  Bijective on [0, nblocks): the last nblocks % (8 kXcdChunk) ids
-// map to themselves.
+// 8 % above the mean.  With CHUNKED false every XCD gets one contiguous run instead, for
+// id ranges whose work is even along them (sun maps: equal sizes, similar content), where
+// it keeps more neighbours under one L2.  Bijective on [0, nblocks): the last
+// nblocks % (8 kXcdChunk) ids map to themselves.
 constexpr int kXcdChunk = 512;
+template <bool CHUNKED = true>
 __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 {
     constexpr int kXcd = 8;
+    if (!CHUNKED) {
+        const int q = nblocks / kXcd, r = nblocks % kXcd;
+        const int x = bid % kXcd, i = bid / kXcd;
+        return x * q + min(x, r) + i;
+    }
     const int full = nblocks - nblocks % (kXcd * kXcdChunk);
     if (bid >= full) return bid;
     const int x = bid % kXcd, i = bid / kXcd;
