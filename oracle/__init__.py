@@ -115,14 +115,17 @@ def forward(scene, settings: Settings = Settings(), vis=None, sel=None):
         m = P
     img = np.zeros(3 * m); A = np.zeros(3 * m); Vo = np.zeros(m); D = np.zeros(m)
     N = np.zeros(3 * m); T = np.zeros(m); cnt = np.zeros(m, np.int64); amb = np.zeros(m, np.uint8)
+    sig = np.zeros(m, np.uint64)
     st = settings.c()
     L = lib()
     L.or_forward(C.c_int64(n), *[_p(a) for a in arrs], C.c_int32(nv), _p(W), _p(H), _p(F),
                  _p(dF), _p(cC), _p(cc), _p(am), _p(vis), C.c_float(scene["b_z"]),
                  C.byref(st), C.c_int64(m if sel is not None else 0), _p(sel),
-                 _p(img), _p(A), _p(Vo), _p(D), _p(N), _p(T), _p(cnt), _p(amb))
+                 _p(img), _p(A), _p(Vo), _p(D), _p(N), _p(T), _p(cnt), _p(amb), _p(sig))
+    # sig: per-pixel digest of the discrete decisions (contributing surfels, stop, branch,
+    # clamp, degenerate flags); equal digests mean the forward is smooth between two inputs
     return dict(image=img, albedo=A, vis=Vo, depth=D, normal=N, T=T, count=cnt,
-                ambiguous=amb.astype(bool))
+                ambiguous=amb.astype(bool), sig=sig)
 
 
 def backward(scene, dI, dD, dN, settings: Settings = Settings(), vis=None, sel=None):
@@ -208,20 +211,27 @@ def sun_camera(scene, v, S=1024):
     return Bs.reshape(2, 3), bs, zf.value
 
 
-def sun_depth(scene, Bs, bs, zfar, texels, settings: Settings = Settings()):
+def sun_depth(scene, Bs, bs, zfar, texels, settings: Settings = Settings(),
+              with_ambiguity=False):
+    """Sun-view depth at the given texels; with_ambiguity also returns the per-texel
+    threshold-ambiguity flags of the compositing (same protocol as the main views)."""
     arrs = _surf_args(scene["surfels"])[:5]
     n = arrs[0].shape[0]
     tex = np.ascontiguousarray(texels, np.int32).reshape(-1, 2)
     out = np.zeros(tex.shape[0])
+    amb = np.zeros(tex.shape[0], np.uint8)
     st = settings.c()
     lib().or_sun_depth(C.c_int64(n), *[_p(a) for a in arrs],
                        _p(np.ascontiguousarray(Bs, np.float64).ravel()),
                        _p(np.ascontiguousarray(bs, np.float64)), C.c_float(scene["b_z"]),
-                       C.c_double(zfar), C.byref(st), C.c_int64(tex.shape[0]), _p(tex), _p(out))
-    return out
+                       C.c_double(zfar), C.byref(st), C.c_int64(tex.shape[0]), _p(tex), _p(out),
+                       _p(amb))
+    return (out, amb.astype(bool)) if with_ambiguity else out
 
 
-def shadow(scene, v, settings: Settings = Settings(), sel=None):
+def shadow(scene, v, settings: Settings = Settings(), sel=None, with_ambiguity=False):
+    """Per-surfel sun visibility of view v; with_ambiguity also returns, per surfel,
+    whether any of its 3x3 sun-map texels is threshold-ambiguous."""
     arrs = _surf_args(scene["surfels"])[:5]
     n = arrs[0].shape[0]
     m = n
@@ -229,12 +239,13 @@ def shadow(scene, v, settings: Settings = Settings(), sel=None):
         sel = np.ascontiguousarray(sel, np.int64)
         m = sel.shape[0]
     out = np.zeros(m)
+    amb = np.zeros(m, np.uint8)
     st = settings.c()
     lib().or_shadow(C.c_int64(n), *[_p(a) for a in arrs], _p(_f32(scene["Fxy"])),
                     _p(_f32(scene.get("dF"))), _p(_f32(scene["sun"])), C.c_int32(v),
                     C.c_float(scene["b_z"]), C.c_int32(settings.sun_map_size), C.byref(st),
-                    C.c_int64(m if sel is not None else 0), _p(sel), _p(out))
-    return out
+                    C.c_int64(m if sel is not None else 0), _p(sel), _p(out), _p(amb))
+    return (out, amb.astype(bool)) if with_ambiguity else out
 
 
 def num_threads():

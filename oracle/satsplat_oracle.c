@@ -171,7 +171,21 @@ typedef struct {
     double A[3], V, D, N[3], T;
     int64_t count;
     int ambiguous;
+    uint64_t sig;           /* digest of the pixel's discrete decisions (test support) */
 } or_px;
+
+/* Folds one decision into a pixel's signature (FNV-1a over 64-bit words).  The
+ * signature changes whenever the set of contributing surfels, a branch, a clamp, a
+ * degenerate flag or a normal orientation changes; finite-difference tests use it to discard steps that cross
+ * a discontinuity. */
+static uint64_t sig_mix(uint64_t h, uint64_t word)
+{
+    for (int b = 0; b < 8; ++b) {
+        h ^= (word >> (8 * b)) & 0xFFu;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
 
 /* Front-to-back compositing (Eq. rasterization) at pixel centre x over all surfels in
  * the global depth order.  If hits != NULL the contributing pairs are recorded. */
@@ -181,6 +195,7 @@ static void render_pixel(const or_proj *pj, const int64_t *order, int64_t n, dou
 {
     double T = 1.0;
     memset(out, 0, sizeof *out);
+    out->sig = 1469598103934665603ull;
     const double inv_s2 = 1.0 / (st->sigma * st->sigma);
     for (int64_t r = 0; r < n; ++r) {
         const or_proj *p = &pj[order[r]];
@@ -202,7 +217,13 @@ static void render_pixel(const or_proj *pj, const int64_t *order, int64_t n, dou
         if (alpha < st->alpha_min) continue;
         double Tn = T * (1.0 - alpha);
         if (fabs(Tn - st->T_min) <= 1e-5 * st->T_min) out->ambiguous = 1;
-        if (Tn < st->T_min) break;
+        if (Tn < st->T_min) {
+            out->sig = sig_mix(out->sig, ~(uint64_t)order[r]);
+            break;
+        }
+        out->sig = sig_mix(out->sig, (uint64_t)order[r] << 4 | (uint64_t)(p->nsign < 0) << 3 |
+                                     (uint64_t)ub << 2 | (uint64_t)(oG >= st->alpha_max) << 1 |
+                                     (uint64_t)p->degenerate);
         if (fabs(oG - st->alpha_max) <= 1e-5) out->ambiguous = 1;
         if (!p->degenerate && p->filter_on && fabs(rho_u - rho_f) <= 1e-5 * rho)
             out->ambiguous = 1;
@@ -270,7 +291,7 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
                 const float *vis, float bz, const or_settings *st,
                 int64_t nsel, const int64_t *sel,
                 double *img, double *Aout, double *Vout, double *Dout, double *Nout,
-                double *Tout, int64_t *count, uint8_t *ambig)
+                double *Tout, int64_t *count, uint8_t *ambig, uint64_t *sig)
 {
     int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv + 1));
     poff[0] = 0;
@@ -308,6 +329,7 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
                 }
                 Vout[s] = Vp; Dout[s] = px.D; Tout[s] = px.T; count[s] = px.count;
                 ambig[s] = (uint8_t)px.ambiguous;
+                if (sig) sig[s] = px.sig;
             } else {
                 int64_t b3 = 3 * poff[v];
                 for (int ch = 0; ch < 3; ++ch) {
@@ -316,6 +338,7 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
                 }
                 Vout[g] = Vp; Dout[g] = px.D; Tout[g] = px.T; count[g] = px.count;
                 ambig[g] = (uint8_t)px.ambiguous;
+                if (sig) sig[g] = px.sig;
             }
         }
         free(pj);
@@ -631,7 +654,7 @@ void or_sun_camera(int64_t n, const float *mean, const float *Fxy, const float *
 void or_sun_depth(int64_t n, const float *mean, const float *tu, const float *tv,
                   const float *scale, const float *opac, const double *Bs6,
                   const double *bs2, float bz, double zfar, const or_settings *st,
-                  int64_t ntex, const int32_t *tex, double *out)
+                  int64_t ntex, const int32_t *tex, double *out, uint8_t *ambig)
 {
     or_cam cam;
     for (int r = 0; r < 2; ++r) {
@@ -651,6 +674,7 @@ void or_sun_depth(int64_t n, const float *mean, const float *tu, const float *tv
         or_px px;
         render_pixel(pj, order, n, tex[2 * t] + 0.5, tex[2 * t + 1] + 0.5, st, 0, &px, NULL, 0);
         out[t] = px.D + px.T * zfar;
+        if (ambig) ambig[t] = (uint8_t)px.ambiguous;
     }
     free(order);
     free(pj);
@@ -666,7 +690,7 @@ void or_sun_depth(int64_t n, const float *mean, const float *tu, const float *tv
 void or_shadow(int64_t n, const float *mean, const float *tu, const float *tv,
                const float *scale, const float *opac, const float *Fxy, const float *dF,
                const float *sun, int32_t v, float bz, int32_t S, const or_settings *st,
-               int64_t nsel, const int64_t *sel, double *vis_out)
+               int64_t nsel, const int64_t *sel, double *vis_out, uint8_t *ambig_out)
 {
     double Bs[6], bs[2], zfar;
     or_sun_camera(n, mean, Fxy, dF, sun, v, bz, S, Bs, bs, &zfar);
@@ -690,7 +714,8 @@ void or_shadow(int64_t n, const float *mean, const float *tu, const float *tv,
         }
     }
     double *D = (double *)malloc(sizeof(double) * 9 * (size_t)(m > 0 ? m : 1));
-    or_sun_depth(n, mean, tu, tv, scale, opac, Bs, bs, bz, zfar, st, 9 * m, tex, D);
+    uint8_t *tamb = (uint8_t *)malloc(9 * (size_t)(m > 0 ? m : 1));
+    or_sun_depth(n, mean, tu, tv, scale, opac, Bs, bs, bz, zfar, st, 9 * m, tex, D, tamb);
     for (int64_t s = 0; s < m; ++s) {
         int64_t k = sel ? sel[s] : s;
         double dk = (double)bz - mean[3 * k + 2];
@@ -701,7 +726,13 @@ void or_shadow(int64_t n, const float *mean, const float *tu, const float *tv,
         }
         acc /= 9.0;
         vis_out[s] = acc < 1.0 ? acc : 1.0;
+        if (ambig_out) {
+            uint8_t a = 0;
+            for (int t = 0; t < 9; ++t) a |= inside[9 * s + t] ? tamb[9 * s + t] : 0;
+            ambig_out[s] = a;
+        }
     }
+    free(tamb);
     free(D);
     free(inside);
     free(tex);

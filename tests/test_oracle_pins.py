@@ -49,11 +49,14 @@ def pixel_centres(W, H):
 
 
 # ---------------------------------------------------------------- P1 analytic Gaussian
-def test_p1_horizontal_surfel_nadir_camera_is_analytic_gaussian():
+@pytest.mark.parametrize("o", [0.8, 0.995, 0.999])
+def test_p1_horizontal_surfel_nadir_camera_is_analytic_gaussian(o):
     """Sec. 3.2 Eqs. affine2dgs_screen2uv / affine2dgs_Qq + depth function: a horizontal
-    surfel under a nadir camera renders an axis-aligned Gaussian of std s/g pixels."""
+    surfel under a nadir camera renders an axis-aligned Gaussian of std s/g pixels,
+    alpha = min(0.99, o exp(-rho/2)).  With o > 0.99 the clamp is active near the centre
+    (alpha_max reading of Eq. rasterization)."""
     g, W, H = 0.5, 48, 40
-    su, sv, o, a, pz = 3.0, 1.7, 0.8, (0.3, 0.6, 0.9), 4.0
+    su, sv, a, pz = 3.0, 1.7, (0.3, 0.6, 0.9), 4.0
     sc = custom_scene([dict(p=(1.3, -0.7, pz), tu=(1, 0, 0), tv=(0, 1, 0), s=(su, sv), o=o, a=a)],
                       [(W, H, nadir(g, W, H))], bz=50.0)
     out = oracle.forward(sc, ST)
@@ -63,6 +66,8 @@ def test_p1_horizontal_surfel_nadir_camera_is_analytic_gaussian():
     rho = ((xs - cx) * g / su) ** 2 + ((ys - cy) * g / sv) ** 2
     alpha = np.minimum(F32(0.99), o * np.exp(-0.5 * rho))
     alpha = np.where(alpha >= ST.alpha_min, alpha, 0.0)
+    clamped = o * np.exp(-0.5 * rho) > F32(0.99)
+    assert clamped.any() == (o > F32(0.99))
     A = planar(out, "albedo", W, H, 3)
     for ch in range(3):
         np.testing.assert_allclose(A[ch], a[ch] * alpha, atol=1e-12)
@@ -448,6 +453,45 @@ def test_p13_binning_box_contains_every_contributing_pixel():
                 continue
             assert pix[k, 0] <= ii.min() and ii.max() <= pix[k, 1]
             assert pix[k, 2] <= jj.min() and jj.max() <= pix[k, 3]
+
+
+def test_p13_binning_box_is_tight():
+    """Sec. 3.2 'Rasterization': the FP64 box is no wider than the support it bounds.
+    The support is sampled on a quarter-pixel lattice by rendering each surfel alone with
+    the camera translated by multiples of 1/4 px (the camera-delta translation column,
+    Sec. 3.3: b - d renders the image at x + d); the box may extend past the sampled
+    support by at most 1 px (pixel rounding) plus the lattice step on each side."""
+    W, H, q = 48, 44, 4
+    sc = synth.make_scene(synth.tiny(n_surfels=40, views=((W, H),), seed=3))
+    s = sc["surfels"]
+    s["t_v"][:4] = np.array([0, 0, 1], np.float32)         # edge-on: low-pass disk only
+    s["t_u"][:4] = np.array([1, 0, 0], np.float32)
+    B, b = oracle.view_camera(sc, 0)
+    checked = 0
+    for mode in (0, 1):
+        st = Settings(lowpass_mode=mode)
+        _, _, pix, _ = oracle.binning(sc, B, b, W, H, 16, st)
+        for k in range(40):
+            one = dict(sc, surfels={kk: v[k:k + 1] for kk, v in s.items()},
+                       colC=None, colc=None, ambient=None)
+            xs, ys = [], []
+            for a in range(q):
+                for c in range(q):
+                    one["dF"] = sc["dF"].copy()
+                    one["dF"][0, 0, 3] -= np.float32(a / q)
+                    one["dF"][0, 1, 3] -= np.float32(c / q)
+                    hit = oracle.forward(one, st)["count"].reshape(H, W) > 0
+                    jj, ii = np.nonzero(hit)
+                    xs.extend(ii + 0.5 + a / q)
+                    ys.extend(jj + 0.5 + c / q)
+            if pix[k, 0] > pix[k, 1]:
+                continue
+            assert xs, f"surfel {k}: non-empty box but no support sample"
+            slack = 1.0 + 1.0 / q
+            assert pix[k, 0] + 0.5 >= min(xs) - slack and pix[k, 1] + 0.5 <= max(xs) + slack, k
+            assert pix[k, 2] + 0.5 >= min(ys) - slack and pix[k, 3] + 0.5 <= max(ys) + slack, k
+            checked += 1
+    assert checked > 40
 
 
 def test_tile_lists_from_ranges_small_example():
