@@ -236,10 +236,12 @@ ss_status ss_step(ss_plan *plan, const ss_surfels *s, const ss_views *v, const s
 
 /* Capture ss_step with these exact pointers into a HIP graph (no host synchronisation
  * and no memset nodes inside; grids are sized by the bound pair capacities, counts stay
- * on the device).  Replays read the current contents of all input buffers.  After a
- * replay, ss_plan_check reports whether the data needed more pairs than bound; then
- * rebind a larger workspace and rebuild the graph.  The plan's settings and workspace
- * must not change while the graph exists. */
+ * on the device).  Replays read the current contents of all input buffers.  A replay
+ * does not check capacity: after a replay the caller must call ss_plan_check, which
+ * reports whether the data needed more pairs than bound (the outputs are then incomplete);
+ * then rebind a larger workspace and rebuild the graph.  Binding a workspace or changing
+ * the settings invalidates every graph captured from the plan: ss_graph_launch then
+ * returns SS_ERR_STATE and launches nothing.  The plan must outlive its graphs. */
 ss_status ss_graph_build(ss_plan *plan, const ss_surfels *s, const ss_views *v,
                          const ss_step_io *io, ss_graph **out);
 ss_status ss_graph_launch(ss_graph *graph, ss_stream stream);

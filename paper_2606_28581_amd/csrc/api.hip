@@ -99,6 +99,9 @@ struct ss_plan {
     size_t ws_bytes = 0;
     Layout L{};
     bool fwd_valid = false, sun_valid = false;
+    // bumped whenever the workspace or the settings change: a captured graph holds raw
+    // pointers into the workspace and kernels specialised for the settings
+    uint64_t generation = 1;
     uint32_t *order_main = nullptr, *order_sun = nullptr;
     uint32_t *lists_main = nullptr, *lists_sun = nullptr;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -367,35 +370,47 @@ static ss_status upload_views(ss_plan *p)
 }
 
 // ------------------------------------------------------------------ surrogate MLP
+// Byte offsets of the MLP's buffers for batches of up to `maxp` points: BF16 / FP32 weight
+// copies, saved features and activations, logits, activation gradients, per-block partial
+// weight gradients and output-layer partials.  constexpr so that the allocation-free
+// training entry point can size its static scratch array at compile time.
+struct MlpLayout {
+    size_t o_wb = 0, o_wf = 0, o_F = 0, o_H = 0, o_logit = 0, o_dA = 0, o_pdw = 0, o_pdb = 0,
+           o_pout = 0, total = 0;
+};
+
+static constexpr MlpLayout mlp_layout_for(int64_t maxp)
+{
+    MlpLayout L{};
+    size_t o = 0;
+    auto take = [&o](size_t b) { size_t r = o; o += (b + 255) & ~size_t(255); return r; };
+    const size_t M = (size_t)(maxp > 0 ? maxp : 0);
+    const size_t nblk = (M + kDwChunk - 1) / kDwChunk;   // mlp_dw_blocks(M)
+    const size_t nout = (M + 255) / 256;
+    L.o_wb = take(kMlpBf16 * 2);
+    L.o_wf = take(kMlpF32 * 4);
+    L.o_F = take(M * kMlpIn * 2);
+    L.o_H = take(3 * M * kMlpWidth * 2);
+    L.o_logit = take(M * 4);
+    L.o_dA = take(2 * M * kMlpWidth * 2);
+    L.o_pdw = take(nblk * kMlpWidth * kMlpIn * 4);
+    L.o_pdb = take(nblk * kMlpWidth * 4);
+    L.o_pout = take(nout * 66 * 4);
+    L.total = o;
+    return L;
+}
+
 struct ss_mlp {
     ss_context *ctx = nullptr;
     ss_mlp_config cfg{};
     char *ws = nullptr;
     size_t bytes = 0;
     int64_t maxp = 0;
-    size_t o_wb = 0, o_wf = 0, o_F = 0, o_H = 0, o_logit = 0, o_dA = 0, o_pdw = 0, o_pdb = 0,
-           o_pout = 0, total = 0;
+    MlpLayout L{};
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
 
-static void mlp_layout(ss_mlp *m, int64_t maxp)
-{
-    size_t o = 0;
-    auto take = [&](size_t b) { size_t r = o; o += align256(b); return r; };
-    const size_t M = (size_t)std::max<int64_t>(maxp, 0);
-    const size_t nblk = (size_t)mlp_dw_blocks((int64_t)M);
-    const size_t nout = (M + 255) / 256;
-    m->o_wb = take(kMlpBf16 * 2);
-    m->o_wf = take(kMlpF32 * 4);
-    m->o_F = take(M * kMlpIn * 2);
-    m->o_H = take(3 * M * kMlpWidth * 2);
-    m->o_logit = take(M * 4);
-    m->o_dA = take(2 * M * kMlpWidth * 2);
-    m->o_pdw = take(nblk * kMlpWidth * kMlpIn * 4);
-    m->o_pdb = take(nblk * kMlpWidth * 4);
-    m->o_pout = take(nout * 66 * 4);
-    m->total = o;
-}
+static void mlp_layout(ss_mlp *m, int64_t maxp) { m->L = mlp_layout_for(maxp); }
 
 static MlpNorm mlp_norm(const ss_mlp *m)
 {
@@ -503,6 +518,7 @@ ss_status ss_plan_set_settings(ss_plan *p, const ss_raster_settings *settings)
     p->st = *settings;
     build_views(p);
     p->fwd_valid = p->sun_valid = false;
+    ++p->generation;
     return upload_views(p);
 }
 
@@ -530,6 +546,7 @@ ss_status ss_plan_bind_workspace(ss_plan *p, void *workspace, size_t bytes, int6
     p->cap_main = main_pairs;
     p->cap_sun = sun_pairs;
     p->fwd_valid = p->sun_valid = false;
+    ++p->generation;
     return upload_views(p);
 }
 
@@ -767,6 +784,7 @@ struct ss_graph {
     ss_plan *plan = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t generation = 0;   // the plan's generation at capture
 };
 
 static ss_status check_io(const ss_plan *p, const ss_views *v, const ss_step_io *io)
@@ -834,6 +852,7 @@ ss_status ss_graph_build(ss_plan *p, const ss_surfels *s, const ss_views *v, con
     G->plan = p;
     G->graph = g;
     G->exec = x;
+    G->generation = p->generation;
     *out = G;
     return SS_OK;
 }
@@ -841,6 +860,9 @@ ss_status ss_graph_build(ss_plan *p, const ss_surfels *s, const ss_views *v, con
 ss_status ss_graph_launch(ss_graph *G, ss_stream stream)
 {
     if (!G || !G->exec) return fail(SS_ERR_INVALID_ARG, "graph is NULL");
+    if (G->generation != G->plan->generation)
+        return fail(SS_ERR_STATE, "the plan's workspace or settings changed since the graph "
+                                  "was captured; rebuild the graph");
     SS_HIP(hipSetDevice(G->plan->ctx->device));
     SS_HIP(hipGraphLaunch(G->exec, reinterpret_cast<hipStream_t>(stream)));
     return SS_OK;
@@ -957,7 +979,7 @@ ss_status ss_mlp_workspace_size(ss_mlp *m, int64_t max_points, size_t *bytes)
     if (!m || !bytes || max_points < 0) return fail(SS_ERR_INVALID_ARG, "bad arguments");
     ss_mlp tmp;
     mlp_layout(&tmp, max_points);
-    *bytes = tmp.total;
+    *bytes = tmp.L.total;
     return SS_OK;
 }
 
@@ -966,7 +988,7 @@ ss_status ss_mlp_bind_workspace(ss_mlp *m, void *ws, size_t bytes, int64_t max_p
     if (!m || !ws || max_points < 0) return fail(SS_ERR_INVALID_ARG, "bad arguments");
     if (((uintptr_t)ws & 255) != 0) return fail(SS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     mlp_layout(m, max_points);
-    if (bytes < m->total) return fail(SS_ERR_CAPACITY, "workspace smaller than required");
+    if (bytes < m->L.total) return fail(SS_ERR_CAPACITY, "workspace smaller than required");
     m->ws = reinterpret_cast<char *>(ws);
     m->bytes = bytes;
     m->maxp = max_points;
@@ -983,32 +1005,33 @@ ss_status ss_mlp_forward(ss_mlp *m, const float *w, const float *pts, int64_t n_
     if (!all_pairs && n_pts != n_sun) return fail(SS_ERR_INVALID_ARG, "paired mode needs n_pts == n_sun");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     SS_HIP(hipSetDevice(m->ctx->device));
-    SS_HIP(launch_mlp_prep(w, m->at<uint16_t>(m->o_wb), m->at<float>(m->o_wf), st));
+    SS_HIP(launch_mlp_prep(w, m->at<uint16_t>(m->L.o_wb), m->at<float>(m->L.o_wf), st));
     const int64_t M = all_pairs ? n_pts * n_sun : n_pts;
-    SS_HIP(launch_mlp_forward(m->at<uint16_t>(m->o_wb), m->at<float>(m->o_wf), pts, sun, M,
+    SS_HIP(launch_mlp_forward(m->at<uint16_t>(m->L.o_wb), m->at<float>(m->L.o_wf), pts, sun, M,
                               all_pairs ? n_pts : 0, mlp_norm(m), prob != 0, out, nullptr, nullptr,
                               st));
     return SS_OK;
 }
 
-ss_status ss_mlp_backward(ss_mlp *m, const float *w, const float *pts, const float *sun, int64_t M,
-                          const float *labels, const float *d_logits, float scale, float *d_w,
-                          float *loss, ss_stream stream)
+}  // extern "C"
+
+// MLP backward (recomputing forward + BCE / given-logit-gradient adjoint + weight
+// gradients) with its buffers at `base` laid out by L (L sized for >= M points).
+static ss_status mlp_backward_at(const ss_mlp *m, char *base, const MlpLayout &L, const float *w,
+                                 const float *pts, const float *sun, int64_t M,
+                                 const float *labels, const float *d_logits, float scale,
+                                 float *d_w, float *loss, hipStream_t st)
 {
-    if (!m || !m->ws) return fail(SS_ERR_STATE, "MLP has no workspace");
-    if (!w || !pts || !sun || !d_w || (!labels && !d_logits))
-        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
-    if (M < 1 || M > m->maxp) return fail(SS_ERR_CAPACITY, "M must be in [1, max_points]");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    SS_HIP(hipSetDevice(m->ctx->device));
-    uint16_t *wb = m->at<uint16_t>(m->o_wb);
-    float *wf = m->at<float>(m->o_wf);
-    uint16_t *F = m->at<uint16_t>(m->o_F);
-    uint16_t *H = m->at<uint16_t>(m->o_H);
+    auto at16 = [base](size_t off) { return reinterpret_cast<uint16_t *>(base + off); };
+    auto at32 = [base](size_t off) { return reinterpret_cast<float *>(base + off); };
+    uint16_t *wb = at16(L.o_wb);
+    float *wf = at32(L.o_wf);
+    uint16_t *F = at16(L.o_F);
+    uint16_t *H = at16(L.o_H);
     uint16_t *H1 = H, *H2 = H + M * kMlpWidth, *H3 = H + 2 * M * kMlpWidth;
-    uint16_t *dA0 = m->at<uint16_t>(m->o_dA), *dA1 = dA0 + M * kMlpWidth;
-    float *logit = m->at<float>(m->o_logit);
-    float *pdw = m->at<float>(m->o_pdw), *pdb = m->at<float>(m->o_pdb), *pout = m->at<float>(m->o_pout);
+    uint16_t *dA0 = at16(L.o_dA), *dA1 = dA0 + M * kMlpWidth;
+    float *logit = at32(L.o_logit);
+    float *pdw = at32(L.o_pdw), *pdb = at32(L.o_pdb), *pout = at32(L.o_pout);
     const int nblk = mlp_dw_blocks(M);
     const int nout = (int)((M + 255) / 256);
     SS_HIP(launch_mlp_prep(w, wb, wf, st));
@@ -1032,6 +1055,21 @@ ss_status ss_mlp_backward(ss_mlp *m, const float *w, const float *pts, const flo
     SS_HIP(launch_mlp_reduce(pdw, nblk, kMlpW1, kMlpW1, d_w + kOffW1, st));
     SS_HIP(launch_mlp_reduce(pdb, nblk, kMlpWidth, kMlpWidth, d_w + kOffB1, st));
     return SS_OK;
+}
+
+extern "C" {
+
+ss_status ss_mlp_backward(ss_mlp *m, const float *w, const float *pts, const float *sun, int64_t M,
+                          const float *labels, const float *d_logits, float scale, float *d_w,
+                          float *loss, ss_stream stream)
+{
+    if (!m || !m->ws) return fail(SS_ERR_STATE, "MLP has no workspace");
+    if (!w || !pts || !sun || !d_w || (!labels && !d_logits))
+        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    if (M < 1 || M > m->maxp) return fail(SS_ERR_CAPACITY, "M must be in [1, max_points]");
+    SS_HIP(hipSetDevice(m->ctx->device));
+    return mlp_backward_at(m, m->ws, m->L, w, pts, sun, M, labels, d_logits, scale, d_w, loss,
+                           reinterpret_cast<hipStream_t>(stream));
 }
 
 ss_status ss_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,
@@ -1062,8 +1100,8 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
     SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
     {
         StageScope scope(p, SS_STAGE_MLP, st);
-        SS_HIP(launch_mlp_prep(w, mlp->at<uint16_t>(mlp->o_wb), mlp->at<float>(mlp->o_wf), st));
-        SS_HIP(launch_mlp_forward(mlp->at<uint16_t>(mlp->o_wb), mlp->at<float>(mlp->o_wf), s->mean,
+        SS_HIP(launch_mlp_prep(w, mlp->at<uint16_t>(mlp->L.o_wb), mlp->at<float>(mlp->L.o_wf), st));
+        SS_HIP(launch_mlp_forward(mlp->at<uint16_t>(mlp->L.o_wb), mlp->at<float>(mlp->L.o_wf), s->mean,
                                   v->sun, p->n * (int64_t)p->nv, p->n, mlp_norm(mlp), true, vis,
                                   nullptr, nullptr, st));
     }

@@ -578,13 +578,20 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                 ncontrib += (int)__popcll(cmc);
             }
             if (CM && cmask) {
-                const int P0 = pos0 + c0, w = P0 >> 6;
+                // chunk positions [P0, P0 + cnt) fall in word P0 / 64 and, when the batch
+                // depth does not divide 64, also in the next word
+                const int P0 = pos0 + c0, w = P0 >> 6, sh = P0 & 63;
                 if (w != wcur) {
                     if (wcur >= 0) cmask[(wbase + wcur) * 64 + tid] = wacc;
                     wacc = 0ull;
                     wcur = w;
                 }
-                wacc |= cmc << (P0 & 63);
+                wacc |= cmc << sh;
+                if (sh + cnt > 64) {
+                    cmask[(wbase + wcur) * 64 + tid] = wacc;
+                    wacc = cmc >> (64 - sh);
+                    wcur = w + 1;
+                }
             }
         }
         if (!__syncthreads_or(!done)) break;
@@ -926,9 +933,12 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
 // then through alpha = min(alpha_max, o G), G = exp(-rho/2), rho = |Q delta|^2 or
 // |delta|^2 / sigma^2, delta = x - c, z = z0 - k . u.  Each 16-lane row of a wave owns a
 // 4x4 quadrant of the wave's 8x8 pixels and walks, back to front, only the staged records
-// whose box meets that quadrant (4 ballots per chunk of 64 give the row masks); the 16
-// record-gradient values are reduced within the row and added with one atomic per lane,
-// so one instruction carries the sums of up to four records.
+// that any of its pixels composited in the forward (8x8 tiles: the forward's contributor
+// masks) or whose box meets the quadrant (other tile sizes: 4 ballots per chunk of 64).
+// A lane takes part in a pair only where the forward composited it - its own mask bit, or
+// the forward's box and alpha tests - so the walk revisits exactly the forward's pairs.
+// The 16 record-gradient values are reduced within the row and added with one atomic per
+// lane, so one instruction carries the sums of up to four records.
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
 template <int TS, bool HAS_VIS>
@@ -1031,13 +1041,18 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
         if (kb > 0) SS_FETCH_BWD(bb - batch, batch);
         for (int c0 = ((nb - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
             const int cnt = min(64, nb - c0);
-            uint64_t m = 0;
+            uint64_t m = 0, own = 0;
             if (use_cm) {
-                // the row walks the records any of its 16 pixels composited in the forward
-                const int P0 = bb + c0;
-                uint64_t cb = inside ? cmask[(wbase + (P0 >> 6)) * 64 + pidx] >> (P0 & 63) : 0ull;
-                cb &= cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
-                m = row_or64(cb);
+                // the row walks the records any of its 16 pixels composited in the forward;
+                // a lane takes part only where its own pixel did (its forward mask bit)
+                const int P0 = bb + c0, sh = P0 & 63;
+                const unsigned long long *wp = cmask + (wbase + (P0 >> 6)) * 64 + pidx;
+                if (inside) {
+                    own = wp[0] >> sh;
+                    if (sh != 0 && sh + cnt > 64) own |= wp[64] << (64 - sh);
+                }
+                own &= cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+                m = row_or64(own);
             } else {
             // lane t tests chunk record c0 + t against the wave's four 4x4 quadrants
             uint32_t qbits = 0;
@@ -1071,7 +1086,20 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 // contribute (outside [0, last) or alpha < alpha_min) get zero gradients
                 // and leave T and the suffix unchanged
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
-                const bool contrib = act && bb + j < mylast && e.alpha >= rc.alpha_min;
+                // the forward's own decision for this pair: its mask bit (8x8 tiles), else
+                // the same FP32 alpha test inside the pixel's FP64 box (the forward never
+                // evaluates a pair outside it)
+                bool fwd_took;
+                if (use_cm) {
+                    fwd_took = (own >> jl) & 1ull;
+                } else {
+                    const uint32_t bx = __float_as_uint(r0.x), by = __float_as_uint(r0.y);
+                    const int xlo = (int)(int16_t)(bx & 0xFFFFu), xhi = (int)(int16_t)(bx >> 16);
+                    const int ylo = (int)(int16_t)(by & 0xFFFFu), yhi = (int)(int16_t)(by >> 16);
+                    fwd_took = px >= xlo && px <= xhi && py >= ylo && py <= yhi &&
+                               e.alpha >= rc.alpha_min;
+                }
+                const bool contrib = act && bb + j < mylast && fwd_took;
                 float gr[16];
                 pair_gradients(e, contrib, r2, r3, r4, r5, pa, HAS_VIS, two_is2, rc.alpha_max, Tr,
                                gS, gr);

@@ -306,13 +306,19 @@ class Graph:
 
     def __init__(self, plan: "Plan", s: SurfelTensors, v: ViewTensors, bufs: StepBuffers):
         h = C.c_void_p()
+        self.plan = plan
         self._keep = (s, v, bufs)
         sc, vc, io = s.c(), v.c(), bufs.c()
         call("ss_graph_build", plan.handle, C.byref(sc), C.byref(vc), C.byref(io), C.byref(h))
         self.handle = h
 
-    def launch(self):
+    def launch(self, check: bool = False):
+        """Replay the step.  With check=True, block and raise if the replay needed more
+        (tile, surfel) pairs than the plan's capacity (its outputs are then incomplete)."""
         call("ss_graph_launch", self.handle, _stream())
+        if check and self.plan.check()[0]:
+            raise RuntimeError("satsplat: pair capacity overflow in a graph replay; rebind a "
+                               "larger workspace and rebuild the graph")
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib._lib is not None:

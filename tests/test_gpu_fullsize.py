@@ -1,13 +1,18 @@
-"""Parity at full size: the 2M-surfel, 40-view workload (sides 1024..2048 px, 1024^2 sun
-maps) in the launch configuration the benchmark times (tile 8, batch depth 64), checked
-on sampled outputs that the FP64 oracle computes one by one, plus properties that hold
-at every pixel.
+"""Parity at full size, in the launch configuration the benchmark times (tile 8, batch
+depth 64), on sampled outputs that the FP64 oracle computes one by one, plus properties
+that hold at every pixel.
 
-The oracle renders the sampled pixels of two views by brute force over all 2M
-surfels.  Visibility enters the forward as an input; only surfels whose FP64 support box
-holds a sampled pixel can contribute there, so the oracle's shadow pass is evaluated for
-exactly those surfels (9 sun-map texels each, brute force) and the same values serve as
-the forward's visibility on both sides.  The GPU's own sun pass is compared with them.
+* 2M surfels, 40 views of sides 1024..2048 px, 1024^2 sun maps: 512 pixels over 8 views,
+  half of them drawn from the 1 % longest 8x8 tile lists (where multi-word contributor
+  masks and long back-to-front walks run); their image, albedo, visibility, depth,
+  normal, transmittance and every gradient they cause.  The sun pass is checked on a
+  sample of surfels, visibility to max-abs 1e-4 where none of a surfel's 3x3 sun-map
+  texels is threshold-ambiguous.
+* 1M surfels, one 2048^2 view with camera delta and colour correction, and 5M surfels
+  on the 2x2 km city, one 2048^2 view: sampled pixels and their gradients.
+
+Visibility enters the forward as a seeded per-(view, surfel) input on both sides; the
+oracle renders each sampled pixel by brute force over all surfels.
 """
 import numpy as np
 import pytest
@@ -20,14 +25,13 @@ from gpu_common import context, oracle_settings, rel_err, to_np
 
 pytestmark = pytest.mark.gpu
 
-VIEWS = (0, 39)
-PER_VIEW = 5
 T_MIN = np.float32(1e-4)
+TS = 8
 
 
 def support_rel_err(a, b):
-    """rel_err over the entries either side sets (the gradients of a few sampled pixels
-    touch a few hundred of the 2M surfels; the rms floor is taken over those)."""
+    """rel_err over the entries either side sets (the gradients of a few hundred sampled
+    pixels touch a small part of the surfels; the rms floor is taken over those)."""
     a = np.asarray(a, np.float64).reshape(-1)
     b = np.asarray(b, np.float64).reshape(-1)
     s = (a != 0) | (b != 0)
@@ -41,107 +45,167 @@ def sub_scene(sc, vs):
                 colc=pick(sc["colc"]), ambient=pick(sc["ambient"]), sun=pick(sc["sun"]))
 
 
+def tile_lengths(sc, v, ost):
+    """Pairs per 8x8 tile of view v from the oracle's FP64 binning (2D difference array
+    over each surfel's tile rectangle)."""
+    W, H = int(sc["width"][v]), int(sc["height"][v])
+    B, b = oracle.view_camera(sc, v)
+    _, _, _, tiles = oracle.binning(sc, B, b, W, H, TS, ost)
+    tx, ty = (W + TS - 1) // TS, (H + TS - 1) // TS
+    live = tiles[:, 0] <= tiles[:, 1]
+    t = tiles[live].astype(np.int64)
+    d = np.zeros((ty + 1, tx + 1), np.int64)
+    np.add.at(d, (t[:, 2], t[:, 0]), 1)
+    np.add.at(d, (t[:, 2], t[:, 1] + 1), -1)
+    np.add.at(d, (t[:, 3] + 1, t[:, 0]), -1)
+    np.add.at(d, (t[:, 3] + 1, t[:, 1] + 1), 1)
+    return np.cumsum(np.cumsum(d, 0), 1)[:ty, :tx]
+
+
+def pick_pixels(sc, views, per_view, long_frac, rng, ost):
+    """Per view: per_view * (1 - long_frac) uniform pixels and the rest inside the 1 %
+    longest tiles.  Returns local pixel indices per view."""
+    out = []
+    for v in views:
+        W, H = int(sc["width"][v]), int(sc["height"][v])
+        n_long = int(per_view * long_frac)
+        uni = rng.choice(W * H, per_view - n_long, replace=False)
+        picks = list(uni)
+        if n_long:
+            L = tile_lengths(sc, v, ost)
+            cut = np.quantile(L, 0.99)
+            ty, tx = np.nonzero(L >= cut)
+            k = rng.choice(ty.size, n_long, replace=True)
+            for a, c in zip(tx[k], ty[k]):
+                i = min(W - 1, a * TS + int(rng.integers(TS)))
+                j = min(H - 1, c * TS + int(rng.integers(TS)))
+                picks.append(j * W + i)
+        out.append(np.unique(np.asarray(picks, np.int64)))
+    return out
+
+
+class Workload:
+    def __init__(self, sc, views, per_view, long_frac, seed, with_sun=False):
+        self.sc = sc
+        self.views = tuple(views)
+        surf, vt = ss.scene_to_device(sc, with_sun=with_sun)
+        st = ss.default_settings(tile_size=TS, batch_depth=64)
+        self.plan = ss.Plan(context(), surf.mean.shape[0], vt.width, vt.height, st)
+        self.plan.ensure_capacity(surf, vt)
+        self.surf, self.vt = surf, vt
+        self.ost = oracle_settings(ts=TS, S=1024)
+        self.sub = sub_scene(sc, self.views)
+        rng = np.random.default_rng(seed)
+        local = pick_pixels(sc, self.views, per_view, long_frac, rng, self.ost)
+        self.off_all = synth.pixel_offsets(sc["width"], sc["height"])
+        off_sub = synth.pixel_offsets(self.sub["width"], self.sub["height"])
+        self.sel_all = np.concatenate([self.off_all[v] + l for v, l in zip(self.views, local)])
+        self.sel_sub = np.concatenate([off_sub[k] + l for k, l in enumerate(local)])
+        n, nv = surf.mean.shape[0], len(sc["width"])
+        self.vis = rng.uniform(0.0, 1.0, size=(nv, n)).astype(np.float32)
+        self.vis_sub = self.vis[list(self.views)]
+        W, H = sc["width"], sc["height"]
+        rows = []
+        for g in self.sel_all:
+            v = int(np.searchsorted(self.off_all, g, side="right") - 1)
+            P, loc = int(W[v]) * int(H[v]), int(g - self.off_all[v])
+            rows.append([3 * self.off_all[v] + ch * P + loc for ch in range(3)])
+        self.rows = np.asarray(rows)
+        self.out = None
+        self.ref = None
+
+    def forward(self):
+        vis = torch.as_tensor(self.vis, device="cuda")
+        out = self.plan.forward(self.surf, self.vt, vis)
+        self.out = out
+        self.ref = oracle.forward(self.sub, self.ost, vis=self.vis_sub, sel=self.sel_sub)
+        return {k: to_np(t) for k, t in out.items()}
+
+    def check_forward(self, o):
+        ref, rows, sel = self.ref, self.rows, self.sel_all
+        ok = ~ref["ambiguous"]
+        assert ok.mean() > 0.99
+        half = self.sc["spec"].extent / 2
+        np.testing.assert_allclose(o["image"][rows][ok], ref["image"].reshape(-1, 3)[ok], atol=1e-4)
+        np.testing.assert_allclose(o["albedo"][rows][ok], ref["albedo"].reshape(-1, 3)[ok], atol=1e-4)
+        np.testing.assert_allclose(o["normal"][rows][ok], ref["normal"].reshape(-1, 3)[ok], atol=1e-4)
+        np.testing.assert_allclose(o["vis"][sel][ok], ref["vis"][ok], atol=1e-4)
+        np.testing.assert_allclose(o["T"][sel][ok], ref["T"][ok], atol=1e-4)
+        np.testing.assert_allclose(o["depth"][sel][ok] / half, ref["depth"][ok] / half, atol=1e-4)
+        return ok
+
+    def check_backward(self, ok, seed):
+        g = np.random.default_rng(seed)
+        m, rows, sel = len(self.sel_all), self.rows, self.sel_all
+        dI_c = (g.standard_normal((m, 3)) * ok[:, None]).astype(np.float32)
+        dD_c = (g.standard_normal(m) * ok).astype(np.float32)
+        dN_c = (g.standard_normal((m, 3)) * ok[:, None]).astype(np.float32)
+        P_all = int(self.off_all[-1])
+        dI = np.zeros(3 * P_all, np.float32); dN = np.zeros(3 * P_all, np.float32)
+        dD = np.zeros(P_all, np.float32)
+        dI[rows.ravel()] = dI_c.ravel(); dN[rows.ravel()] = dN_c.ravel(); dD[sel] = dD_c
+        cu = lambda a: torch.as_tensor(a, device="cuda")
+        gg = self.plan.backward(self.surf, self.vt, self.out, cu(dI), cu(dD), cu(dN),
+                                vis=cu(self.vis))
+        gr = oracle.backward(self.sub, dI_c.ravel(), dD_c, dN_c.ravel(), self.ost,
+                             vis=self.vis_sub, sel=self.sel_sub)
+        for key in ("mean", "t_u", "t_v", "scale", "opacity", "albedo"):
+            assert np.abs(gr[key]).max() > 0, key
+            assert support_rel_err(to_np(gg[key]), gr[key]) < 1e-3, key
+        nv = len(self.sc["width"])
+        for key in ("dF", "colC", "colc", "ambient"):
+            gv = to_np(gg[key])
+            assert rel_err(gv[list(self.views)], gr[key]) < 1e-3, key
+            others = np.setdiff1d(np.arange(nv), self.views)
+            if others.size:
+                assert np.abs(gv[others]).max() == 0.0, key
+
+
+C3_VIEWS = (0, 5, 10, 15, 20, 25, 30, 39)
+
+
 @pytest.fixture(scope="module")
 def c3():
     sc = synth.make_scene(synth.config(3))
-    surf, views = ss.scene_to_device(sc, with_sun=True)
-    st = ss.default_settings(tile_size=8, batch_depth=64)
-    plan = ss.Plan(context(), surf.mean.shape[0], views.width, views.height, st)
-    plan.ensure_capacity(surf, views)
-    sub = sub_scene(sc, VIEWS)
-    rng = np.random.default_rng(77)
-    off_all = synth.pixel_offsets(sc["width"], sc["height"])
-    off_sub = synth.pixel_offsets(sub["width"], sub["height"])
-    sel_all, sel_sub, local = [], [], []
-    for k, v in enumerate(VIEWS):
-        P = int(sc["width"][v]) * int(sc["height"][v])
-        loc = np.sort(rng.choice(P, PER_VIEW, replace=False))
-        local.append(loc)
-        sel_all.append(off_all[v] + loc)
-        sel_sub.append(off_sub[k] + loc)
-    # candidate surfels of each sampled view: FP64 box holds a sampled pixel
-    ost = oracle_settings(ts=8, S=1024)
-    n = sc["surfels"]["mean"].shape[0]
-    cand = []
-    for k, v in enumerate(VIEWS):
-        W, H = int(sc["width"][v]), int(sc["height"][v])
-        B, b = oracle.view_camera(sc, v)
-        _, _, pix, _ = oracle.binning(sc, B, b, W, H, 8, ost)
-        i, j = local[k] % W, local[k] // W
-        hit = np.zeros(n, bool)
-        for ii, jj in zip(i, j):
-            hit |= (pix[:, 0] <= ii) & (ii <= pix[:, 1]) & (pix[:, 2] <= jj) & (jj <= pix[:, 3])
-        cand.append(np.flatnonzero(hit))
-    vis_sub = np.zeros((len(VIEWS), n), np.float32)
-    for k in range(len(VIEWS)):
-        vis_sub[k, cand[k]] = oracle.shadow(sub, k, ost, sel=cand[k])
-    return dict(sc=sc, sub=sub, plan=plan, surf=surf, views=views, ost=ost,
-                sel_all=np.concatenate(sel_all), sel_sub=np.concatenate(sel_sub),
-                off_all=off_all, cand=cand, vis_sub=vis_sub)
+    return Workload(sc, C3_VIEWS, per_view=64, long_frac=0.5, seed=77, with_sun=True)
 
 
-def test_fullsize_sun_pass_matches_oracle_on_candidate_surfels(c3):
-    vis = to_np(c3["plan"].shadow(c3["surf"], c3["views"]))
-    for k, v in enumerate(VIEWS):
-        c = c3["cand"][k]
-        assert c.size > PER_VIEW
-        vg, vref = vis[v, c], c3["vis_sub"][k, c]
-        err = np.abs(vg - vref)
-        assert np.mean(err < 1e-3) > 0.98 and err.max() < 0.5, (v, err.max())
-        far = np.abs(vref - 0.5) > 0.05
-        assert np.all((vg[far] >= 0.5) == (vref[far] >= 0.5)), v
-
-
-def test_fullsize_forward_and_backward_match_oracle_on_sampled_pixels(c3):
-    sc, plan, surf, views = c3["sc"], c3["plan"], c3["surf"], c3["views"]
-    n, nv = surf.mean.shape[0], len(sc["width"])
-    vis = torch.zeros(nv, n, device="cuda")
-    for k, v in enumerate(VIEWS):
-        vis[v] = torch.as_tensor(c3["vis_sub"][k], device="cuda")
-    out = plan.forward(surf, views, vis)
-    o = {k: to_np(t) for k, t in out.items()}
-    # properties at every pixel of every view
+def test_c3_forward_sampled_pixels_and_every_pixel_properties(c3):
+    o = c3.forward()
     for key in ("image", "albedo", "vis", "depth", "normal", "T"):
         assert np.all(np.isfinite(o[key])), key
     assert o["T"].min() >= T_MIN and o["T"].max() <= 1.0
-    # sampled pixels vs brute force
-    ref = oracle.forward(c3["sub"], c3["ost"], vis=c3["vis_sub"], sel=c3["sel_sub"])
-    ok = ~ref["ambiguous"]
-    assert ok.sum() >= len(c3["sel_sub"]) - 2
-    off, W, H = c3["off_all"], sc["width"], sc["height"]
-    rows = []
-    for g in c3["sel_all"]:
-        v = int(np.searchsorted(off, g, side="right") - 1)
-        P, loc = int(W[v]) * int(H[v]), int(g - off[v])
-        rows.append([3 * off[v] + ch * P + loc for ch in range(3)])
-    rows = np.asarray(rows)
-    sel = c3["sel_all"]
-    half = sc["spec"].extent / 2
-    np.testing.assert_allclose(o["image"][rows][ok], ref["image"].reshape(-1, 3)[ok], atol=1e-4)
-    np.testing.assert_allclose(o["albedo"][rows][ok], ref["albedo"].reshape(-1, 3)[ok], atol=1e-4)
-    np.testing.assert_allclose(o["normal"][rows][ok], ref["normal"].reshape(-1, 3)[ok], atol=1e-4)
-    np.testing.assert_allclose(o["vis"][sel][ok], ref["vis"][ok], atol=1e-4)
-    np.testing.assert_allclose(o["T"][sel][ok], ref["T"][ok], atol=1e-4)
-    np.testing.assert_allclose(o["depth"][sel][ok] / half, ref["depth"][ok] / half, atol=1e-4)
-    # upstream gradients only at the non-ambiguous sampled pixels
-    g = np.random.default_rng(78)
-    m = len(sel)
-    dI_c = (g.standard_normal((m, 3)) * ok[:, None]).astype(np.float32)
-    dD_c = (g.standard_normal(m) * ok).astype(np.float32)
-    dN_c = (g.standard_normal((m, 3)) * ok[:, None]).astype(np.float32)
-    P_all = int(off[-1])
-    dI = np.zeros(3 * P_all, np.float32); dN = np.zeros(3 * P_all, np.float32)
-    dD = np.zeros(P_all, np.float32)
-    dI[rows.ravel()] = dI_c.ravel(); dN[rows.ravel()] = dN_c.ravel(); dD[sel] = dD_c
-    cu = lambda a: torch.as_tensor(a, device="cuda")
-    gg = plan.backward(surf, views, out, cu(dI), cu(dD), cu(dN), vis=vis)
-    gr = oracle.backward(c3["sub"], dI_c.ravel(), dD_c, dN_c.ravel(), c3["ost"],
-                         vis=c3["vis_sub"], sel=c3["sel_sub"])
-    for key in ("mean", "t_u", "t_v", "scale", "opacity", "albedo"):
-        assert np.abs(gr[key]).max() > 0, key
-        assert support_rel_err(to_np(gg[key]), gr[key]) < 1e-3, key
-    for key in ("dF", "colC", "colc", "ambient"):
-        gv = to_np(gg[key])
-        assert rel_err(gv[list(VIEWS)], gr[key]) < 1e-3, key
-        others = np.setdiff1d(np.arange(nv), VIEWS)
-        assert np.abs(gv[others]).max() == 0.0, key
+    assert len(c3.sel_all) >= 500
+    c3.ok = c3.check_forward(o)
+
+
+def test_c3_backward_sampled_pixels(c3):
+    if c3.out is None:
+        pytest.skip("needs the forward test's outputs")
+    c3.check_backward(c3.ok, seed=78)
+
+
+def test_c3_sun_pass_on_sampled_surfels(c3):
+    vis = to_np(c3.plan.shadow(c3.surf, c3.vt))
+    rng = np.random.default_rng(79)
+    n = c3.surf.mean.shape[0]
+    for v in (0, 39):
+        sel = np.sort(rng.choice(n, 96, replace=False))
+        one = sub_scene(c3.sc, (v,))
+        vref, amb = oracle.shadow(one, 0, c3.ost, sel=sel, with_ambiguity=True)
+        vg = vis[v, sel]
+        assert amb.mean() < 0.1
+        err = np.abs(vg - vref)[~amb]
+        assert err.max() <= 1e-4, (v, err.max())
+
+
+@pytest.mark.parametrize("cfg", [2, 5])
+def test_single_view_sampled_pixels(cfg):
+    """1M surfels on the 1 km city and 5M on the 2 km city, one 2048^2 view each."""
+    spec = synth.config(cfg, views=[(2048, 2048)]) if cfg == 5 else synth.config(cfg)
+    sc = synth.make_scene(spec)
+    w = Workload(sc, (0,), per_view=96, long_frac=0.5, seed=80 + cfg)
+    o = w.forward()
+    assert np.all(np.isfinite(o["image"])) and o["T"].min() >= T_MIN
+    ok = w.check_forward(o)
+    w.check_backward(ok, seed=90 + cfg)

@@ -131,8 +131,8 @@ def test_forward_config1_full_image():
 
 
 # ---------------------------------------------------------------- backward
-def check_backward(sc, plan, surf, views, out, ref, vis=None, tol=1e-3):
-    st = oracle_settings()
+def check_backward(sc, plan, surf, views, out, ref, vis=None, tol=1e-3, mode=0):
+    st = oracle_settings(mode=mode)
     dI, dD, dN = synth.upstream_grads(sc)
     W, H = sc["width"], sc["height"]
     amb = ref["ambiguous"]
@@ -149,10 +149,10 @@ def check_backward(sc, plan, surf, views, out, ref, vis=None, tol=1e-3):
     return errs
 
 
-@pytest.mark.parametrize("ts,batch", [(16, 64), (8, 64), (8, 32)])
+@pytest.mark.parametrize("ts,batch", [(16, 64), (8, 64), (8, 32), (8, 48), (8, 7), (32, 100)])
 def test_backward_multiview_with_colour_and_vis(ts, batch):
-    """8x8 tiles take the contributor-mask walk (batch 32: the backward's batches then
-    split the forward's 64-position mask words)."""
+    """8x8 tiles take the contributor-mask walk: batch 32 splits the forward's 64-position
+    mask words, batch 48 and 7 make chunks that straddle two words."""
     sc = scene_tiny(seed=13)
     vis = np.random.default_rng(2).uniform(size=(3, 400)).astype(np.float32)
     plan, surf, views = make_plan(sc, ts=ts, batch=batch)
@@ -170,6 +170,8 @@ def test_backward_config1():
 
 
 def test_autograd_function_matches_plan_backward():
+    """torch.autograd.Function around the library's adjoint: gradients of a loss through
+    rasterize() equal the oracle's (upstream gradient zeroed on ambiguous pixels)."""
     import paper_2606_28581_amd as ss
     sc = scene_tiny(seed=14, views=((30, 30),), n=200)
     plan, surf, views = make_plan(sc)
@@ -178,17 +180,68 @@ def test_autograd_function_matches_plan_backward():
     for p in params:
         p.requires_grad_(True)
     o = ss.rasterize(plan, views, surf)
+    ref = oracle.forward(sc, oracle_settings())
     dI, dD, dN = synth.upstream_grads(sc)
+    amb = ref["ambiguous"]
+    amb3 = expand3(amb, sc["width"], sc["height"])
+    dI[amb3] = 0; dN[amb3] = 0; dD[amb] = 0
     t = lambda a: torch.as_tensor(a, device="cuda")
     L = (o["image"] * t(dI)).sum() + (o["depth"] * t(dD)).sum() + (o["normal"] * t(dN)).sum()
     L.backward()
-    ref = oracle.forward(sc, oracle_settings())
-    amb3 = expand3(ref["ambiguous"], sc["width"], sc["height"])
-    assert not ref["ambiguous"].any() or True
     gref = oracle.backward(sc, dI, dD, dN, oracle_settings())
-    if not ref["ambiguous"].any():
-        for k, p in zip(GRAD_KEYS, params):
-            assert rel_err(to_np(p.grad), gref[k]) < 1e-3, k
+    for k, p in zip(GRAD_KEYS, params):
+        assert p.grad is not None, k
+        assert rel_err(to_np(p.grad), gref[k]) < 1e-3, k
+
+
+# ------------------------------------------------------- clamp and degenerate branches
+@pytest.mark.parametrize("ts,batch,mode", [(8, 64, 0), (8, 48, 1), (16, 64, 0), (16, 64, 1)])
+def test_clamped_and_degenerate_surfels_forward_and_backward(ts, batch, mode):
+    """Surfels with o G above alpha_max (alpha clamped to 0.99; the backward recovers T by
+    dividing by 1 - 0.99) and degenerate surfels (edge-on in an oblique view, det T = 0
+    exactly in a nadir view: no uv branch, low-pass disk only) at 8x8 (contributor-mask
+    walk) and 16x16 (box walk) tiles, both low-pass modes."""
+    from branch_scenes import branch_scene, special_surfels
+    sc = branch_scene()
+    n = sc["surfels"]["mean"].shape[0]
+    V = len(sc["width"])
+    vis = np.random.default_rng(3).uniform(size=(V, n)).astype(np.float32)
+    plan, surf, views = make_plan(sc, ts=ts, batch=batch, mode=mode)
+    out = plan.forward(surf, views, torch.as_tensor(vis, device="cuda"))
+    st = oracle_settings(ts=ts, mode=mode)
+    ref = oracle.forward(sc, st, vis=vis)
+    check_forward(sc, out, ref, sc["spec"].extent / 2)
+    # the clamp changes this scene's render (the branch is reached)
+    noclamp = oracle.forward(sc, oracle.Settings(lowpass_mode=mode,
+                                                 alpha_max=np.float32(0.99999).item()), vis=vis)
+    assert np.abs(noclamp["image"] - ref["image"]).max() > 1e-3
+    errs = check_backward(sc, plan, surf, views, out, ref, vis=vis, mode=mode)
+    clamp, deg = special_surfels(sc)
+    gref = oracle.backward(sc, *synth.upstream_grads(sc), st, vis=vis)
+    assert np.abs(gref["mean"][deg]).max() > 0 and np.abs(gref["albedo"][clamp]).max() > 0
+
+
+def test_graph_is_invalidated_by_rebinding_and_settings_changes():
+    """A captured graph holds raw workspace pointers: after the plan's workspace is
+    rebound, or its settings change, a replay is refused instead of running stale."""
+    import paper_2606_28581_amd as ss
+    sc = scene_tiny(seed=15)
+    plan, surf, views = make_plan(sc)
+    dI, dD, dN = [torch.as_tensor(x, device="cuda") for x in synth.upstream_grads(sc)]
+    bufs = ss.StepBuffers(surf.mean.shape[0], views.width, views.height, with_sun=False,
+                          upstream=(dI, dD, dN))
+    g = ss.Graph(plan, surf, views, bufs)
+    g.launch(check=True)
+    torch.cuda.synchronize()
+    plan.bind(plan.cap_main + 4096, plan.cap_sun)
+    with pytest.raises(ss.SatSplatError):
+        g.launch()
+    g2 = ss.Graph(plan, surf, views, bufs)
+    g2.launch(check=True)
+    plan.set_settings(ss.default_settings(tile_size=8, batch_depth=32))
+    with pytest.raises(ss.SatSplatError):
+        g2.launch()
+    torch.cuda.synchronize()
 
 
 # ---------------------------------------------------------------- edge cases
@@ -226,18 +279,26 @@ def test_capacity_overflow_regrows_and_matches():
         np.testing.assert_array_equal(to_np(out[k]), to_np(ref_out[k]))
 
 
-def test_forward_deterministic_backward_nearly():
+@pytest.mark.parametrize("ts", [8, 16])
+def test_forward_deterministic_backward_nearly(ts):
+    """The forward is bitwise reproducible; the backward's float atomics reorder sums, so
+    repeated backwards differ by rounding only.  Prints the measured spread over 8 runs."""
     sc = scene_tiny(seed=6)
-    plan, surf, views = make_plan(sc)
+    plan, surf, views = make_plan(sc, ts=ts)
     a = {k: to_np(v) for k, v in plan.forward(surf, views).items()}
     out = plan.forward(surf, views)
     for k in a:
         np.testing.assert_array_equal(to_np(out[k]), a[k])
     dI, dD, dN = [torch.as_tensor(x, device="cuda") for x in synth.upstream_grads(sc)]
     g1 = {k: to_np(v).copy() for k, v in plan.backward(surf, views, out, dI, dD, dN).items()}
-    g2 = plan.backward(surf, views, out, dI, dD, dN)
+    spread = {k: 0.0 for k in GRAD_KEYS}
+    for _ in range(8):
+        g2 = plan.backward(surf, views, out, dI, dD, dN)
+        for k in GRAD_KEYS:
+            spread[k] = max(spread[k], rel_err(to_np(g2[k]), g1[k]))
+    print(f"atomic-order spread ts={ts}: " + ", ".join(f"{k} {v:.2e}" for k, v in spread.items()))
     for k in GRAD_KEYS:
-        assert rel_err(to_np(g2[k]), g1[k]) < ATOMIC_ORDER_TOL, k
+        assert spread[k] < ATOMIC_ORDER_TOL, k
 
 
 def test_pair_count_scan_beyond_one_pass_of_the_partials_kernel():
