@@ -84,6 +84,10 @@ def pick_pixels(sc, views, per_view, long_frac, rng, ost):
     return out
 
 
+def n_views_str(sc):
+    return f"{sc['spec'].n_surfels} surfels, {len(sc['width'])} views"
+
+
 class Workload:
     def __init__(self, sc, views, per_view, long_frac, seed, with_sun=False):
         self.sc = sc
@@ -99,6 +103,7 @@ class Workload:
         local = pick_pixels(sc, self.views, per_view, long_frac, rng, self.ost)
         self.off_all = synth.pixel_offsets(sc["width"], sc["height"])
         off_sub = synth.pixel_offsets(self.sub["width"], self.sub["height"])
+        print(f"[fullsize] {n_views_str(sc)}: plan sized, pixels picked", flush=True)
         self.sel_all = np.concatenate([self.off_all[v] + l for v, l in zip(self.views, local)])
         self.sel_sub = np.concatenate([off_sub[k] + l for k, l in enumerate(local)])
         n, nv = surf.mean.shape[0], len(sc["width"])
@@ -119,6 +124,7 @@ class Workload:
         out = self.plan.forward(self.surf, self.vt, vis)
         self.out = out
         self.ref = oracle.forward(self.sub, self.ost, vis=self.vis_sub, sel=self.sel_sub)
+        print(f"[fullsize] forward of {len(self.sel_all)} pixels: GPU and oracle done", flush=True)
         return {k: to_np(t) for k, t in out.items()}
 
     def check_forward(self, o):
@@ -149,6 +155,7 @@ class Workload:
                                 vis=cu(self.vis))
         gr = oracle.backward(self.sub, dI_c.ravel(), dD_c, dN_c.ravel(), self.ost,
                              vis=self.vis_sub, sel=self.sel_sub)
+        print(f"[fullsize] backward of {m} pixels: GPU and oracle done", flush=True)
         for key in ("mean", "t_u", "t_v", "scale", "opacity", "albedo"):
             assert np.abs(gr[key]).max() > 0, key
             assert support_rel_err(to_np(gg[key]), gr[key]) < 1e-3, key
