@@ -296,6 +296,20 @@ ss_status ss_mlp_forward(ss_mlp *mlp, const float *w, const float *pts, int64_t 
 ss_status ss_mlp_backward(ss_mlp *mlp, const float *w, const float *pts, const float *sun,
                           int64_t M, const float *labels, const float *d_logits, float scale,
                           float *d_w, float *loss, ss_stream stream);
+/* Allocation-free variant of ss_mlp_backward, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight training or serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and rounding as ss_mlp_backward (the same
+ * kernels run), but the MLP needs no bound workspace: the buffers live in a fixed device
+ * array inside the library of 15.1 MiB per device (held from library load until the
+ * process ends), laid out for M <= SS_NOALLOC_MAX_POINTS points; a larger M returns
+ * SS_ERR_CAPACITY and launches nothing.  The call allocates nothing, device or host
+ * memory.  All calls on one device share that array: calls that overlap on one device
+ * (two streams, two threads) race and must be ordered by the caller.  The device address
+ * of the array is taken when the context is created (ss_context_create). */
+#define SS_NOALLOC_MAX_POINTS 16384
+ss_status ss_mlp_backward_noalloc(ss_mlp *mlp, const float *w, const float *pts, const float *sun,
+                                  int64_t M, const float *labels, const float *d_logits,
+                                  float scale, float *d_w, float *loss, ss_stream stream);
 /* Adam on FP32 master weights (step counts from 1). */
 ss_status ss_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr,
                       float beta1, float beta2, float eps, int32_t step, ss_stream stream);

@@ -97,6 +97,8 @@ _SIGS = {
     "ss_mlp_forward": (C.c_int32, [_P, _P, _P, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32,
                                    _P, _P]),
     "ss_mlp_backward": (C.c_int32, [_P, _P, _P, _P, C.c_int64, _P, _P, C.c_float, _P, _P, _P]),
+    "ss_mlp_backward_noalloc": (C.c_int32, [_P, _P, _P, _P, C.c_int64, _P, _P, C.c_float, _P, _P,
+                                            _P]),
     "ss_mlp_adam": (C.c_int32, [_P, _P, _P, _P, C.c_int64, C.c_float, C.c_float, C.c_float,
                                 C.c_float, C.c_int32, _P]),
     "ss_shadow_surrogate": (C.c_int32, [_P, _P, _P, C.POINTER(Surfels), C.POINTER(Views),
@@ -105,6 +107,7 @@ _SIGS = {
 
 SS_NUM_STAGES = 14
 SS_MLP_PARAMS = 16641
+SS_NOALLOC_MAX_POINTS = 16384
 
 _lib = None
 

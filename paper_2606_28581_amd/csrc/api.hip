@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,7 @@ struct ss_context {
     int device = 0;
     int cus = 0;
     std::string arch;
+    char *scratch = nullptr;   // this device's address of the allocation-free MLP scratch
 };
 
 // Offsets (bytes) of every buffer inside the workspace.
@@ -400,6 +402,38 @@ static constexpr MlpLayout mlp_layout_for(int64_t maxp)
     return L;
 }
 
+// Allocation-free MLP backward (ss_mlp_backward_noalloc): its buffers live in this fixed
+// device array, laid out for batches of up to kNoAllocMaxPoints points (15.1 MiB), not in
+// a bound workspace.  Every device holds its own copy.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in symbol): the device
+// address comes from hipGetSymbolAddress, once per device, when a context is created on
+// it (scratch_address), and only that address is used.
+constexpr int64_t kNoAllocMaxPoints = 16384;
+constexpr MlpLayout kNoAllocLayout = mlp_layout_for(kNoAllocMaxPoints);
+static __device__ __align__(256) char scratch[kNoAllocLayout.total];
+static_assert(kNoAllocLayout.total <= (size_t(16) << 20), "no-alloc scratch must stay modest");
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once with that device current.
+static ss_status scratch_address(int device, char **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return SS_OK;   // entry point refuses later
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        SS_HIP(hipSetDevice(device));
+        SS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(SS_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[device] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return SS_OK;
+}
+
 struct ss_mlp {
     ss_context *ctx = nullptr;
     ss_mlp_config cfg{};
@@ -453,10 +487,14 @@ ss_status ss_context_create(int32_t device, ss_context **out)
     std::string arch = prop.gcnArchName;
     if (arch.rfind("gfx950", 0) != 0)
         return fail(SS_ERR_UNSUPPORTED, "device is " + arch + ", this library is built for gfx950");
+    char *scr = nullptr;
+    ss_status e = scratch_address(device, &scr);
+    if (e != SS_OK) return e;
     auto *c = new ss_context;
     c->device = device;
     c->cus = prop.multiProcessorCount;
     c->arch = arch;
+    c->scratch = scr;
     *out = c;
     return SS_OK;
 }
@@ -1070,6 +1108,22 @@ ss_status ss_mlp_backward(ss_mlp *m, const float *w, const float *pts, const flo
     SS_HIP(hipSetDevice(m->ctx->device));
     return mlp_backward_at(m, m->ws, m->L, w, pts, sun, M, labels, d_logits, scale, d_w, loss,
                            reinterpret_cast<hipStream_t>(stream));
+}
+
+ss_status ss_mlp_backward_noalloc(ss_mlp *m, const float *w, const float *pts, const float *sun,
+                                  int64_t M, const float *labels, const float *d_logits,
+                                  float scale, float *d_w, float *loss, ss_stream stream)
+{
+    if (!m || !m->ctx) return fail(SS_ERR_INVALID_ARG, "mlp is NULL");
+    if (!w || !pts || !sun || !d_w || (!labels && !d_logits))
+        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    if (M < 1 || M > kNoAllocMaxPoints)
+        return fail(SS_ERR_CAPACITY, "M must be in [1, SS_NOALLOC_MAX_POINTS = " +
+                                         std::to_string(kNoAllocMaxPoints) + "]");
+    if (!m->ctx->scratch) return fail(SS_ERR_STATE, "no scratch array on this device");
+    SS_HIP(hipSetDevice(m->ctx->device));
+    return mlp_backward_at(m, m->ctx->scratch, kNoAllocLayout, w, pts, sun, M, labels, d_logits,
+                           scale, d_w, loss, reinterpret_cast<hipStream_t>(stream));
 }
 
 ss_status ss_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float beta1,

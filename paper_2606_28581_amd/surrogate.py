@@ -17,7 +17,8 @@ N_PARAMS = _lib.SS_MLP_PARAMS
 class Mlp:
     """The surrogate network: normalisation constants + a training workspace."""
 
-    def __init__(self, ctx: Context, centre, inv_half: float, max_points: int = 0):
+    def __init__(self, ctx: Context, centre, inv_half: float, max_points: int | None = 0):
+        """max_points=None binds no workspace (only backward_noalloc may then run)."""
         cfg = MlpConfig()
         cfg.struct_size = C.sizeof(MlpConfig)
         for i in range(3):
@@ -27,7 +28,8 @@ class Mlp:
         call("ss_mlp_create", ctx.handle, C.byref(cfg), C.byref(h))
         self.handle, self.ctx, self.max_points = h, ctx, 0
         self.workspace = None
-        self.bind(max_points)
+        if max_points is not None:
+            self.bind(max_points)
 
     def bind(self, max_points: int):
         b = C.c_size_t()
@@ -56,6 +58,16 @@ class Mlp:
         if d_w is None:
             d_w = torch.empty(N_PARAMS, dtype=torch.float32, device=pts.device)
         call("ss_mlp_backward", self.handle, _ptr(w), _ptr(pts), _ptr(sun), pts.shape[0],
+             _ptr(labels), _ptr(d_logits), float(scale), _ptr(d_w), _ptr(loss), _stream())
+        return d_w
+
+    def backward_noalloc(self, w, pts, sun, labels=None, d_logits=None, scale=1.0, d_w=None,
+                         loss=None):
+        """ss_mlp_backward_noalloc: the same gradient with the library's fixed scratch array
+        instead of this object's workspace (up to SS_NOALLOC_MAX_POINTS points)."""
+        if d_w is None:
+            d_w = torch.empty(N_PARAMS, dtype=torch.float32, device=pts.device)
+        call("ss_mlp_backward_noalloc", self.handle, _ptr(w), _ptr(pts), _ptr(sun), pts.shape[0],
              _ptr(labels), _ptr(d_logits), float(scale), _ptr(d_w), _ptr(loss), _stream())
         return d_w
 
