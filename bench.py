@@ -26,13 +26,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# FP32 vector peak without packed dual-FP32 issue (the library is compiled with packed
-# FP32 operations disabled):
-# 256 CU x 64 FMA lanes/clk x 2 flop x 2.4 GHz.
-VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-# Algorithmic FP32 flops per contributing (pixel, surfel) pair (FMA = 2, exp = 4):
-FLOPS_FWD_PAIR = 46
-FLOPS_BWD_PAIR = 90
+# Published FP32 vector peak of the MI355X: 256 CU x 2.4 GHz x 256 flop/clk (it counts
+# packed dual-FP32 FMAs).  The library is compiled with packed FP32 operations disabled,
+# so its own issue ceiling is half of that (64 FMA lanes per CU and clock):
+VALU_PEAK_TFLOPS = 157.3
+VALU_NONPACKED_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# Algorithmic FP32 flops per contributing (pixel, surfel) pair: ~30 operations and one
+# exponential (counted as 4) in the forward, ~80 in the backward.
+FLOPS_FWD_PAIR = 34
+FLOPS_BWD_PAIR = 80
+
+
+def raster_kernel_bytes(kernel, P, K):
+    """Algorithmic HBM bytes of one launch of a raster kernel over all views (P pixels,
+    K (tile, surfel) pairs): the forward reads a 72-byte record (and its list entry) per
+    pair and writes 52 bytes per pixel (image, albedo, V, depth, normal, T, last); the
+    backward reads 68 bytes per pixel (upstream image, depth and normal gradients, saved
+    albedo, V, T, last), re-reads each pair's record and adds its 64-byte record gradient."""
+    if kernel == "raster_fwd":
+        return 72 * K + 52 * P
+    return 68 * P + (72 + 64) * K
 
 
 # HBM bytes per launch measured with the profiler's byte counters (FETCH_SIZE, WRITE_SIZE,
@@ -77,10 +90,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="eager steps instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--cpu-pixels", type=int, default=512)
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training / evaluating the learned shadow surrogate")
     ap.add_argument("--surrogate-epochs", type=int, default=30)
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the training-step-scale run (5M surfels, 50 views of 2048^2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB (5 times) and exit; "
                          "used to calibrate the profiler's FETCH_SIZE / WRITE_SIZE counters")
@@ -103,7 +118,35 @@ def algorithmic_step_bytes(N, V, P, K, Ks, S, Nv=None, Nvs=None):
     return per_step + fwd + bwd + sun
 
 
-def cpu_baseline(scene, n_pix, seed=5):
+def copy_bandwidth(mib=2048, reps=10):
+    """Achievable HBM bandwidth: a plain device-to-device copy, bytes read + written per
+    second, timed with HIP events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    return 2 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, n_pix, seed=5, n_pix_1t=16):
     import numpy as np
     import oracle
     oracle.build(force=False)
@@ -120,13 +163,24 @@ def cpu_baseline(scene, n_pix, seed=5):
     dI = g.standard_normal(3 * n_pix).astype(np.float32)
     dD = g.standard_normal(n_pix).astype(np.float32)
     dN = g.standard_normal(3 * n_pix).astype(np.float32)
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     oracle.forward(scene1, st, sel=sel)
     t1 = time.perf_counter()
     oracle.backward(scene1, dI, dD, dN, st, sel=sel)
     t2 = time.perf_counter()
-    return dict(value=n_pix / (t2 - t0) / 1e6, unit="Mpix/s", cores=oracle.num_threads(),
-                kind="oracle",
+    # one thread, on the first n_pix_1t pixels of the same sample
+    s1 = sel[:n_pix_1t]
+    oracle.set_threads(1)
+    t3 = time.perf_counter()
+    oracle.forward(scene1, st, sel=s1)
+    oracle.backward(scene1, dI[:3 * n_pix_1t], dD[:n_pix_1t], dN[:3 * n_pix_1t], st, sel=s1)
+    t4 = time.perf_counter()
+    oracle.set_threads(cores)
+    return dict(value=n_pix / (t2 - t0) / 1e6, unit="Mpix/s", cores=cores,
+                kind="oracle", cpu=cpu_model(),
+                one_thread=dict(value=n_pix_1t / (t4 - t3) / 1e6, unit="Mpix/s",
+                                sample=f"first {n_pix_1t} pixels of the sample, {t4 - t3:.1f} s"),
                 sample=f"{n_pix} seeded pixels of view 0 ({W}x{H}), forward {t1 - t0:.1f} s + "
                        f"backward {t2 - t1:.1f} s, FP64 brute force over all {scene['surfels']['mean'].shape[0]} "
                        f"surfels per pixel, no shadow pass")
@@ -160,7 +214,7 @@ def surrogate_eval(ctx, args):
     return out
 
 
-def training_scale(args):
+def training_scale(args, tile=None, batch=None):
     """Full training-step scale: 5M surfels on a 2x2 km city, 50 views of 2048^2.  Per step
     the learned shadow surrogate (plain-pass fallback for |p - 0.5| < 0.1) gives every
     view's surfel visibility, then forward and backward of all views with colour
@@ -181,7 +235,7 @@ def training_scale(args):
     ctx = ss.Context(0)
     surf, views = ss.scene_to_device(scene, with_sun=True)
     N, V, P = surf.mean.shape[0], len(views.width), views.pixels
-    settings = ss.default_settings(tile_size=args.tile, batch_depth=args.batch)
+    settings = ss.default_settings(tile_size=tile or args.tile, batch_depth=batch or args.batch)
     plan = ss.Plan(ctx, N, views.width, views.height, settings)
     K, Ks = plan.ensure_capacity(surf, views)
     log(f"[bench] pairs main {K}, sun {Ks}, pixels {P}, workspace {plan.workspace.numel() / 2**30:.1f} GiB")
@@ -357,20 +411,28 @@ def main():
             kern[name] = dict(avg_ms=ms / n, launches=n, share=ms / n / ms_step)
     log("[bench] stages (avg ms / launch): " + ", ".join(f"{k} {v['avg_ms']:.3f}" for k, v in kern.items()))
     C = stats["contrib"]
-    fwd_ms = kern["raster_fwd"]["avg_ms"]
-    bwd_ms = kern["raster_bwd"]["avg_ms"]
-    cands = {
-        "raster_fwd": (FLOPS_FWD_PAIR * C / (fwd_ms * 1e-3) / 1e12, fwd_ms),
-        "raster_bwd": (FLOPS_BWD_PAIR * C / (bwd_ms * 1e-3) / 1e12, bwd_ms),
-    }
-    dom = max(cands, key=lambda k: cands[k][1])
-    achieved = cands[dom][0]
+    Kp = stats["pairs"]
+    cands = {k: kern[k]["avg_ms"] for k in ("raster_fwd", "raster_bwd")}
+    dom = max(cands, key=cands.get)
+    dom_ms = cands[dom]
+    dom_bytes = raster_kernel_bytes(dom, P, Kp)
+    dom_flops = (FLOPS_FWD_PAIR if dom == "raster_fwd" else FLOPS_BWD_PAIR) * C
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    copy_gbps = copy_bandwidth()
     traffic = measured_traffic(dom, spec.name, plan.settings.tile_size, plan.settings.batch_depth)
-    roofline = dict(kernel=dom, bound="alu", achieved=round(achieved, 3), peak=round(VALU_PEAK_TFLOPS, 1),
-                    unit="TFLOP/s", frac=round(achieved / VALU_PEAK_TFLOPS, 4), traffic=traffic,
-                    avg_ms=round(cands[dom][1], 4),
-                    work=f"{FLOPS_FWD_PAIR if dom == 'raster_fwd' else FLOPS_BWD_PAIR} flop x "
-                         f"{C} contributing pairs per launch")
+    tflops = dom_flops / (dom_ms * 1e-3) / 1e12
+    roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=traffic,
+                    avg_ms=round(dom_ms, 4),
+                    work=f"{dom_bytes} algorithmic bytes per launch "
+                         f"({'72 K + 52 P' if dom == 'raster_fwd' else '68 P + 136 K'}, "
+                         f"P = {P} pixels, K = {Kp} tile-surfel pairs)",
+                    copy=dict(GBps=round(copy_gbps, 1), frac=round(achieved / copy_gbps, 4)),
+                    alu=dict(achieved=round(tflops, 3), peak=VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=round(tflops / VALU_PEAK_TFLOPS, 4),
+                             nonpacked_issue_ceiling=round(VALU_NONPACKED_TFLOPS, 1),
+                             work=f"{FLOPS_FWD_PAIR if dom == 'raster_fwd' else FLOPS_BWD_PAIR} "
+                                  f"flop x {C} contributing pairs per launch"))
     step_bytes = algorithmic_step_bytes(N, V, P, stats["pairs"], stats["sun_pairs"] if has_sun else 0,
                                         S if has_sun else 0)
     result = {
@@ -413,6 +475,16 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")
         result["cpu_baseline"] = cpu_baseline(scene, args.cpu_pixels)
+    if not args.no_c5 and args.config == 3:
+        log("[bench] training-step scale: 5M surfels, 50 views of 2048^2")
+        bufs = graph = plan = None
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        c5 = training_scale(args, tile=8, batch=64)
+        result["training_step_c5"] = {k: c5[k] for k in ("value", "unit", "ms_per_step", "steps_per_s",
+                                                         "steps", "peak_hbm_GB", "config", "pairs",
+                                                         "surrogate", "kernels")}
     print(json.dumps(result), flush=True)
 
 

@@ -250,3 +250,8 @@ def shadow(scene, v, settings: Settings = Settings(), sel=None, with_ambiguity=F
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def set_threads(n: int):
+    """Thread count of the oracle's parallel loops (timing only)."""
+    lib().or_set_threads(C.c_int32(int(n)))

@@ -746,3 +746,13 @@ int32_t or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count for the parallel loops over pixels (timing only; results do not depend on it). */
+void or_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -105,6 +105,7 @@ struct ss_plan {
     // pointers into the workspace and kernels specialised for the settings
     uint64_t generation = 1;
     uint32_t *order_main = nullptr, *order_sun = nullptr;
+    bool sun_order_shared = false;   // the last shadow pass used the main-view order buffers
     uint32_t *lists_main = nullptr, *lists_sun = nullptr;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
@@ -284,6 +285,10 @@ static ss_status prepare(ss_plan *p, const ss_surfels *s, const ss_views *v, boo
     uint32_t *ka = p->at<uint32_t>(sun ? L.sk_a : L.mk_a), *kb = p->at<uint32_t>(sun ? L.sk_b : L.mk_b);
     uint32_t *va = p->at<uint32_t>(sun ? L.sv_a : L.mv_a), *vb = p->at<uint32_t>(sun ? L.sv_b : L.mv_b);
     float *sorted = p->at<float>(sun ? L.sorted_sun : L.sorted_main);
+    if (!sun && p->sun_order_shared) {   // a shadow binning that read these buffers goes stale
+        p->sun_valid = false;
+        p->sun_order_shared = false;
+    }
     StageScope scope(p, SS_STAGE_DEPTH_SORT, st);
     SS_HIP(launch_depth_keys(s->mean, p->n, v->b_z, ka, va, st));
     bool in_b = false;
@@ -635,22 +640,21 @@ ss_status ss_plan_check(ss_plan *p, int32_t *overflowed, int64_t *main_pairs, in
     return SS_OK;
 }
 
-ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
-                     float *image, float *albedo_out, float *vis_out, float *depth,
-                     float *normal, float *T_final, int32_t *last, ss_stream stream)
+}  // extern "C"
+
+// Forward of all views; with `order` given (ss_step) the depth order and rank-ordered
+// parameters already in the main-view buffers are used, else they are computed here.
+static ss_status forward_pass(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                              float *image, float *albedo_out, float *vis_out, float *depth,
+                              float *normal, float *T_final, int32_t *last, hipStream_t st,
+                              uint32_t *order, float *sorted)
 {
-    ss_status e = check_call(p, s, v);
-    if (e != SS_OK) return e;
-    if (!image || !albedo_out || !vis_out || !depth || !normal || !T_final || !last)
-        return fail(SS_ERR_INVALID_ARG, "an output pointer is NULL");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    ss_status e;
     p->fwd_valid = false;
     SS_HIP(fill_u32(p->at<uint32_t>(p->L.flags), 0u, 1, st));
     unsigned long long *stat = p->at<unsigned long long>(p->L.stat_main);
     SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
-    uint32_t *order;
-    float *sorted;
-    if ((e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
+    if (!order && (e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
     if ((e = bin_views(p, v, false, order, sorted, vis, true, st)) != SS_OK) return e;
     const RasterConsts rc = consts(p->st);
     {
@@ -665,6 +669,20 @@ ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const f
     p->order_main = order;
     p->fwd_valid = true;
     return SS_OK;
+}
+
+extern "C" {
+
+ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                     float *image, float *albedo_out, float *vis_out, float *depth,
+                     float *normal, float *T_final, int32_t *last, ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!image || !albedo_out || !vis_out || !depth || !normal || !T_final || !last)
+        return fail(SS_ERR_INVALID_ARG, "an output pointer is NULL");
+    return forward_pass(p, s, v, vis, image, albedo_out, vis_out, depth, normal, T_final, last,
+                        reinterpret_cast<hipStream_t>(stream), nullptr, nullptr);
 }
 
 ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
@@ -715,22 +733,21 @@ ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
     return SS_OK;
 }
 
-ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, float *sun_depth,
-                          float *vis, ss_stream stream)
+}  // extern "C"
+
+// Plain shadow pass; with `order` given (ss_step: the main-view depth order of the same
+// surfels, the order is view independent) no depth sort runs here.
+static ss_status shadow_pass(ss_plan *p, const ss_surfels *s, const ss_views *v, float *sun_depth,
+                             float *vis, hipStream_t st, uint32_t *order, float *sorted)
 {
-    ss_status e = check_call(p, s, v);
-    if (e != SS_OK) return e;
-    if (!v->sun) return fail(SS_ERR_INVALID_ARG, "views.sun is NULL");
-    if (!vis) return fail(SS_ERR_INVALID_ARG, "vis output is NULL");
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    ss_status e;
     const Layout &L = p->L;
     p->sun_valid = false;
     SS_HIP(fill_u32(p->at<uint32_t>(L.flags) + 1, 0u, 1, st));
     unsigned long long *stat = p->at<unsigned long long>(L.stat_sun);
     SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
-    uint32_t *order;
-    float *sorted;
-    if ((e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
+    const bool shared = order != nullptr;
+    if (!shared && (e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
     {
         StageScope scope(p, SS_STAGE_SUN_CAMERA, st);
         SS_HIP(launch_sun_cameras(s->mean, p->n, p->nv, v->Fxy, v->dF, v->sun, v->b_z,
@@ -755,8 +772,22 @@ ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, fl
                                    0.f, st));
     }
     p->order_sun = order;
+    p->sun_order_shared = shared;
     p->sun_valid = true;
     return SS_OK;
+}
+
+extern "C" {
+
+ss_status ss_shadow_plain(ss_plan *p, const ss_surfels *s, const ss_views *v, float *sun_depth,
+                          float *vis, ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!v->sun) return fail(SS_ERR_INVALID_ARG, "views.sun is NULL");
+    if (!vis) return fail(SS_ERR_INVALID_ARG, "vis output is NULL");
+    return shadow_pass(p, s, v, sun_depth, vis, reinterpret_cast<hipStream_t>(stream), nullptr,
+                       nullptr);
 }
 
 ss_status ss_debug_binning(ss_plan *p, int32_t which, uint32_t *order, int32_t *surf_tiles,
@@ -838,12 +869,20 @@ ss_status ss_step(ss_plan *p, const ss_surfels *s, const ss_views *v, const ss_s
 {
     ss_status e = check_io(p, v, io);
     if (e != SS_OK) return e;
-    if (v && v->sun) {
-        e = ss_shadow_plain(p, s, v, io->sun_depth, io->vis, stream);
-        if (e != SS_OK) return e;
-    }
-    e = ss_forward(p, s, v, io->vis, io->image, io->albedo_out, io->vis_out, io->depth,
-                   io->normal, io->T_final, io->last, stream);
+    if ((e = check_call(p, s, v)) != SS_OK) return e;
+    if (!io->image || !io->albedo_out || !io->vis_out || !io->depth || !io->normal ||
+        !io->T_final || !io->last)
+        return fail(SS_ERR_INVALID_ARG, "an output pointer is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // one depth order per step, shared by the sun maps and the views (Sec. 3.3: the
+    // depth row is fixed, so the centre-depth order does not depend on the view)
+    uint32_t *order;
+    float *sorted;
+    if ((e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
+    if (v->sun && (e = shadow_pass(p, s, v, io->sun_depth, io->vis, st, order, sorted)) != SS_OK)
+        return e;
+    e = forward_pass(p, s, v, io->vis, io->image, io->albedo_out, io->vis_out, io->depth,
+                     io->normal, io->T_final, io->last, st, order, sorted);
     if (e != SS_OK) return e;
     return ss_backward(p, s, v, io->vis, io->albedo_out, io->vis_out, io->T_final, io->last,
                        io->d_image, io->d_depth, io->d_normal, io->d_mean, io->d_t_u, io->d_t_v,
@@ -1195,6 +1234,7 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
                                        band, st));
     }
     p->order_sun = order;
+    p->sun_order_shared = false;
     p->sun_valid = true;
     return SS_OK;
 }
