@@ -34,7 +34,8 @@ def build(force: bool = True) -> str:
 class _Settings(C.Structure):
     _fields_ = [("alpha_min", C.c_double), ("alpha_max", C.c_double), ("T_min", C.c_double),
                 ("sigma", C.c_double), ("det_rel_eps", C.c_double),
-                ("lowpass_mode", C.c_int32), ("esm_c", C.c_double), ("esm_bias", C.c_double)]
+                ("lowpass_mode", C.c_int32), ("esm_c", C.c_double), ("esm_bias", C.c_double),
+                ("depth_scale", C.c_double)]
 
 
 @dataclass
@@ -51,10 +52,12 @@ class Settings:
     esm_bias: float = 0.5
     sun_map_size: int = 1024
     tile_size: int = 16
+    depth_scale: float = 1.0     # normalised depth m = z * depth_scale in the distortion
 
     def c(self):
         return _Settings(self.alpha_min, self.alpha_max, self.T_min, self.sigma,
-                         self.det_rel_eps, self.lowpass_mode, self.esm_c, self.esm_bias)
+                         self.det_rel_eps, self.lowpass_mode, self.esm_c, self.esm_bias,
+                         self.depth_scale)
 
 
 _lib = None
@@ -98,9 +101,10 @@ def _views(scene):
         _f32(scene.get("colc")), _f32(scene.get("ambient"))
 
 
-def forward(scene, settings: Settings = Settings(), vis=None, sel=None):
+def forward(scene, settings: Settings = Settings(), vis=None, sel=None, with_dist=False):
     """Render every view (sel None -> full planar CHW layout) or only the global pixel
-    indices in `sel` (compact layout).  Returns a dict of float64 arrays."""
+    indices in `sel` (compact layout).  Returns a dict of float64 arrays; with_dist adds
+    the per-pixel depth distortion 'dist'."""
     s = scene["surfels"]
     arrs = _surf_args(s)
     n = arrs[0].shape[0]
@@ -116,19 +120,27 @@ def forward(scene, settings: Settings = Settings(), vis=None, sel=None):
     img = np.zeros(3 * m); A = np.zeros(3 * m); Vo = np.zeros(m); D = np.zeros(m)
     N = np.zeros(3 * m); T = np.zeros(m); cnt = np.zeros(m, np.int64); amb = np.zeros(m, np.uint8)
     sig = np.zeros(m, np.uint64)
+    dist = np.zeros(m) if with_dist else None
     st = settings.c()
     L = lib()
     L.or_forward(C.c_int64(n), *[_p(a) for a in arrs], C.c_int32(nv), _p(W), _p(H), _p(F),
                  _p(dF), _p(cC), _p(cc), _p(am), _p(vis), C.c_float(scene["b_z"]),
                  C.byref(st), C.c_int64(m if sel is not None else 0), _p(sel),
-                 _p(img), _p(A), _p(Vo), _p(D), _p(N), _p(T), _p(cnt), _p(amb), _p(sig))
+                 _p(img), _p(A), _p(Vo), _p(D), _p(N), _p(T), _p(cnt), _p(amb), _p(sig),
+                 _p(dist))
     # sig: per-pixel digest of the discrete decisions (contributing surfels, stop, branch,
     # clamp, degenerate flags); equal digests mean the forward is smooth between two inputs
-    return dict(image=img, albedo=A, vis=Vo, depth=D, normal=N, T=T, count=cnt,
-                ambiguous=amb.astype(bool), sig=sig)
+    out = dict(image=img, albedo=A, vis=Vo, depth=D, normal=N, T=T, count=cnt,
+               ambiguous=amb.astype(bool), sig=sig)
+    if with_dist:
+        out["dist"] = dist
+    return out
 
 
-def backward(scene, dI, dD, dN, settings: Settings = Settings(), vis=None, sel=None):
+def backward(scene, dI, dD, dN, settings: Settings = Settings(), vis=None, sel=None,
+             dDist=None):
+    """Adjoint of forward(): upstream gradients of the image [.,3], depth, normal [.,3]
+    and (optionally) the per-pixel distortion, in forward()'s layout."""
     s = scene["surfels"]
     arrs = _surf_args(s)
     n = arrs[0].shape[0]
@@ -147,7 +159,7 @@ def backward(scene, dI, dD, dN, settings: Settings = Settings(), vis=None, sel=N
     lib().or_backward(C.c_int64(n), *[_p(a) for a in arrs], C.c_int32(nv), _p(W), _p(H),
                       _p(F), _p(dF), _p(cC), _p(cc), _p(am), _p(vis), C.c_float(scene["b_z"]),
                       C.byref(st), C.c_int64(m), _p(sel), _p(_f32(dI)), _p(_f32(dD)),
-                      _p(_f32(dN)), *[_p(g[k]) for k in ("mean", "t_u", "t_v", "scale",
+                      _p(_f32(dN)), _p(_f32(dDist)), *[_p(g[k]) for k in ("mean", "t_u", "t_v", "scale",
                                                          "opacity", "albedo", "dF", "colC",
                                                          "colc", "ambient")])
     shapes = dict(mean=(n, 3), t_u=(n, 3), t_v=(n, 3), scale=(n, 2), opacity=(n,),

@@ -90,10 +90,14 @@ def render(params, scene, settings, vis=None):
         cb = params["colc"][v] if params.get("colc") is not None else torch.zeros(3, dtype=dt)
         La = params["ambient"][v] if params.get("ambient") is not None else torch.zeros(3, dtype=dt)
         I = (A @ Cm.T + cb) * (Vp[:, None] + (1 - Vp[:, None]) * La)
+        # depth distortion, half the double sum over all ordered pairs of
+        # w_i w_j (m_i - m_j)^2, in its moment form (sum w)(sum w m^2) - (sum w m)^2
+        m = z * getattr(settings, "depth_scale", 1.0)
+        dist = w.sum(1) * (w * m * m).sum(1) - (w * m).sum(1) ** 2
         hw = (H[v], W[v])
         out.append(dict(image=I.T.reshape(3, *hw), albedo=A.T.reshape(3, *hw),
                         vis=Vp.reshape(hw), depth=D.reshape(hw), normal=N.T.reshape(3, *hw),
-                        T=Tf.reshape(hw)))
+                        T=Tf.reshape(hw), dist=dist.reshape(hw)))
     return out
 
 
@@ -107,3 +111,33 @@ def params_from_scene(scene, requires_grad=True):
     for k in ("colC", "colc", "ambient"):
         P[k] = t(scene[k]) if scene.get(k) is not None else None
     return P
+
+
+def normal_loss(depth, T, normal, Fxy, dF, b_z, tau=0.5):
+    """Normal-consistency loss of one view (Sec. 3.2 "Normal Definition", Eq.
+    surface_normal), dense torch statement: depth, T [H, W], normal [3, H, W], dF [2, 4]
+    torch tensors; T is used as a constant.  Same readings as oracle.geom."""
+    dt = torch.float64
+    H, W = depth.shape
+    F = torch.as_tensor(np.asarray(Fxy, np.float64)) + dF
+    Bxy, b = F[:, :3], F[:, 3]
+    M = torch.cat([Bxy, torch.tensor([[0.0, 0.0, -1.0]], dtype=dt)], 0)
+    a = (1.0 - T).detach()
+    cover = a >= tau
+    zbar = torch.where(cover, depth / torch.where(cover, a, torch.ones_like(a)), torch.zeros_like(a))
+    ys, xs = torch.meshgrid(torch.arange(H, dtype=dt) + 0.5, torch.arange(W, dtype=dt) + 0.5,
+                            indexing="ij")
+    rhs = torch.stack([xs - b[0], ys - b[1], zbar - b_z], -1)               # [H, W, 3]
+    ps = torch.linalg.solve(M.expand(H, W, 3, 3), rhs.unsqueeze(-1)).squeeze(-1)
+    gx = ps[1:-1, 2:] - ps[1:-1, :-2]
+    gy = ps[2:, 1:-1] - ps[:-2, 1:-1]
+    n = torch.linalg.cross(gx, gy, dim=-1)
+    d = torch.linalg.cross(Bxy[0].detach(), Bxy[1].detach(), dim=0)
+    if d[2] > 0:
+        d = -d
+    flip = ((n.detach() @ d) > 0)
+    Nd = n / n.norm(dim=-1, keepdim=True)
+    Nd = torch.where(flip[..., None], -Nd, Nd)
+    ok = cover[1:-1, 1:-1] & cover[1:-1, 2:] & cover[1:-1, :-2] & cover[2:, 1:-1] & cover[:-2, 1:-1]
+    dot = (normal[:, 1:-1, 1:-1].permute(1, 2, 0) * Nd).sum(-1)
+    return torch.where(ok, 1.0 - dot, torch.zeros_like(dot)).sum() / (H * W)

@@ -43,6 +43,7 @@ typedef struct {
     double alpha_min, alpha_max, T_min, sigma, det_rel_eps;
     int32_t lowpass_mode;   /* 0: low-pass floor for every surfel; 1: degenerate only */
     double esm_c, esm_bias;
+    double depth_scale;     /* normalised depth m = z * depth_scale (distortion term)  */
 } or_settings;
 
 /* One surfel as seen by one affine camera, everything in FP64. */
@@ -277,6 +278,22 @@ static int view_of(const int64_t *poff, int nv, int64_t g)
     return v;
 }
 
+/* Depth distortion of one pixel (the 2DGS form of the Mip-NeRF 360 distortion the paper
+ * weights in its loss, Supp. B): the sum over ordered pairs of contributors of
+ * w_i w_j (m_i - m_j)^2, m = z * depth_scale, written as the plain double sum. */
+static double pixel_distortion(const or_hit *hits, int64_t count, double ds)
+{
+    double d = 0.0;
+    for (int64_t i = 0; i < count; ++i) {
+        const double wi = hits[i].alpha * hits[i].Tb, mi = hits[i].z * ds;
+        for (int64_t j = 0; j < i; ++j) {
+            const double wj = hits[j].alpha * hits[j].Tb, mj = hits[j].z * ds;
+            d += wi * wj * (mi - mj) * (mi - mj);
+        }
+    }
+    return d;
+}
+
 /*
  * Forward render.  Pixels are addressed by a global index g over the concatenation of
  * all views (view v covers [poff[v], poff[v+1]), row-major inside the view).  If sel is
@@ -291,7 +308,7 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
                 const float *vis, float bz, const or_settings *st,
                 int64_t nsel, const int64_t *sel,
                 double *img, double *Aout, double *Vout, double *Dout, double *Nout,
-                double *Tout, int64_t *count, uint8_t *ambig, uint64_t *sig)
+                double *Tout, int64_t *count, uint8_t *ambig, uint64_t *sig, double *dist)
 {
     int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nv + 1));
     poff[0] = 0;
@@ -306,7 +323,12 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
                                    vis ? vis + (int64_t)v * n : NULL, &cam, bz, st);
         double C[3][3], c[3], La[3];
         colour_terms(colC, colc, amb, v, C, c, La);
-        #pragma omp parallel for schedule(dynamic, 16)
+        #pragma omp parallel
+        {
+        /* the distortion needs every contributor of the pixel */
+        const int64_t max_hits = dist ? (n > 0 ? n : 1) : 0;
+        or_hit *hits = dist ? (or_hit *)malloc(sizeof(or_hit) * (size_t)max_hits) : NULL;
+        #pragma omp for schedule(dynamic, 16)
         for (int64_t s = 0; s < total; ++s) {
             int64_t g = sel ? sel[s] : s;
             if (g < poff[v] || g >= poff[v + 1]) continue;
@@ -314,7 +336,8 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
             int64_t P = poff[v + 1] - poff[v];
             int i = (int)(local % W[v]), j = (int)(local / W[v]);
             or_px px;
-            render_pixel(pj, order, n, i + 0.5, j + 0.5, st, vis != NULL, &px, NULL, 0);
+            render_pixel(pj, order, n, i + 0.5, j + 0.5, st, vis != NULL, &px, hits, max_hits);
+            if (dist) dist[sel ? s : g] = pixel_distortion(hits, px.count, st->depth_scale);
             double Vp = vis ? px.V : 1.0;
             double I[3];
             for (int ch = 0; ch < 3; ++ch) {
@@ -341,6 +364,8 @@ void or_forward(int64_t n, const float *mean, const float *tu, const float *tv,
                 if (sig) sig[g] = px.sig;
             }
         }
+        free(hits);
+        }
         free(pj);
     }
     free(order);
@@ -366,7 +391,7 @@ void or_backward(int64_t n, const float *mean, const float *tu, const float *tv,
                  const float *dF, const float *colC, const float *colc, const float *amb,
                  const float *vis, float bz, const or_settings *st,
                  int64_t nsel, const int64_t *sel,
-                 const float *dI, const float *dD, const float *dN,
+                 const float *dI, const float *dD, const float *dN, const float *dDist,
                  double *g_mean, double *g_tu, double *g_tv, double *g_scale,
                  double *g_opac, double *g_alb, double *g_dF, double *g_colC,
                  double *g_colc, double *g_amb)
@@ -409,6 +434,8 @@ void or_backward(int64_t n, const float *mean, const float *tu, const float *tv,
                     if (dN) gN[ch] = dN[at];
                 }
                 if (dD) gD = dD[sel ? s : g];
+                const double gDist = dDist ? (double)dDist[sel ? s : g] : 0.0;
+                const double ds = st->depth_scale;
                 or_px px;
                 render_pixel(pj, order, n, i + 0.5, j + 0.5, st, vis != NULL, &px, hits,
                              max_hits);
@@ -435,9 +462,22 @@ void or_backward(int64_t n, const float *mean, const float *tu, const float *tv,
                     double gf = gA[0] * p->a[0] + gA[1] * p->a[1] + gA[2] * p->a[2] +
                                 gD * hh->z + gN[0] * p->n[0] + gN[1] * p->n[1] +
                                 gN[2] * p->n[2] + (vis ? gV * p->v : 0.0);
+                    double dz = w * gD;
+                    if (gDist != 0.0) {
+                        /* distortion: d/dw_h and d/dm_h of sum_{i<j} w_i w_j (m_i - m_j)^2 */
+                        const double mh = hh->z * ds;
+                        double cw = 0.0, cm = 0.0;
+                        for (int64_t q = 0; q < px.count; ++q) {
+                            if (q == h) continue;
+                            const double wq = hits[q].alpha * hits[q].Tb, dm = mh - hits[q].z * ds;
+                            cw += wq * dm * dm;
+                            cm += wq * dm;
+                        }
+                        gf += gDist * cw;
+                        dz += gDist * 2.0 * w * cm * ds;
+                    }
                     double dalpha = Tb * gf - gS / (1.0 - a);
                     gS += w * gf;
-                    double dz = w * gD;
                     double dn[3] = {w * gN[0], w * gN[1], w * gN[2]};
                     double dO = 0, dG = 0;
                     if (hh->oG < st->alpha_max) { dO = hh->G * dalpha; dG = p->o * dalpha; }
