@@ -181,6 +181,59 @@ ss_status ss_backward(ss_plan *plan, const ss_surfels *s, const ss_views *v,
                       float *d_albedo, float *d_dF, float *d_colC, float *d_colc,
                       float *d_ambient, ss_stream stream);
 
+/* ------------------------------------------------ geometric regularisers
+ * Depth distortion (the distortion term of the paper's training loss, Supp. B, in the
+ * squared 2DGS form): per pixel
+ *     dist = sum over pairs i > j of its contributors of w_i w_j (m_i - m_j)^2,
+ * m = z * depth_scale the normalised depth of each (pixel, surfel) pair.  The forward
+ * variant composites it as an extra channel; the backward variant adds its adjoint for an
+ * upstream gradient d_dist.  aux is state the forward saves for the backward (the depth of
+ * the pixel's first contributor and two moments of the depths relative to it, which keep
+ * the moments from cancelling in FP32).  P = sum of width*height. */
+typedef struct ss_geom_io {
+    uint32_t struct_size;   /* sizeof(ss_geom_io)                                      */
+    float    depth_scale;   /* m = z * depth_scale, > 0 (e.g. 1 / scene half extent)   */
+    float   *dist;          /* [P] forward output; unused by the backward              */
+    float   *aux;           /* [3, P] written by the forward, read by the backward     */
+    const float *d_dist;    /* [P] upstream gradient for the backward, or NULL (= 0)   */
+} ss_geom_io;
+
+/* ss_forward with the distortion channel (same arguments and outputs, plus geom). */
+ss_status ss_forward_geom(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                          const float *vis, float *image, float *albedo_out, float *vis_out,
+                          float *depth, float *normal, float *T_final, int32_t *last,
+                          const ss_geom_io *geom, ss_stream stream);
+/* ss_backward plus the adjoint of the distortion for geom->d_dist; geom->aux must hold
+ * what ss_forward_geom saved for the same inputs. */
+ss_status ss_backward_geom(ss_plan *plan, const ss_surfels *s, const ss_views *v,
+                           const float *vis, const float *albedo_out, const float *vis_out,
+                           const float *T_final, const int32_t *last, const float *d_image,
+                           const float *d_depth, const float *d_normal, const ss_geom_io *geom,
+                           float *d_mean, float *d_t_u, float *d_t_v, float *d_scale,
+                           float *d_opacity, float *d_albedo, float *d_dF, float *d_colC,
+                           float *d_colc, float *d_ambient, ss_stream stream);
+
+/* Depth-gradient normals and the normal-consistency loss (Sec. 3.2 "Normal Definition",
+ * Eq. surface_normal) on the rendered maps of all views.  Per view v with P_v pixels:
+ * the expected depth zbar = D / (1 - T) (the accumulated opacity is a constant: no
+ * gradient flows into T) is back-projected through F' = F + dF with the fixed depth row
+ * (world point p with B'_xy p + b'_xy = pixel centre, b_z - p_z = zbar); N_d is the
+ * normalised cross product of the central differences of that point map along x and y,
+ * oriented like the rendered normals (against B'_x x B'_y taken with negative z);
+ *     loss[v] = weight / P_v * sum over valid pixels of (1 - N . N_d),
+ * N the composited normal map.  A pixel is valid when it is not on the view's border
+ * and 1 - T >= tau at it and at its four neighbours.
+ *   depth [P], T_final [P], normal [3P]: the forward's outputs (planar per view).
+ *   loss [n_views] (written), normal_d [3P] (written, 0 where invalid) or NULL.
+ *   d_depth [P], d_normal [3P], d_dF [n_views,2,4] or NULL: gradients of sum_v loss[v],
+ *   ADDED to what they hold, so that the image loss's upstream gradients can be
+ *   accumulated in the same buffers before ss_backward(_geom).
+ * Uses the plan's workspace (bound) and its views; sizes are those of the plan. */
+ss_status ss_normal_loss(ss_plan *plan, const ss_views *v, const float *depth,
+                         const float *T_final, const float *normal, float weight, float tau,
+                         float *loss, float *normal_d, float *d_depth, float *d_normal,
+                         float *d_dF, ss_stream stream);
+
 /* -------------------------------------------------------------- shadow pass
  * Geometric sun-view shadow map (Sec. 3.3 Eq. sun_camera_Bxy, Supp. A; Sec. 3.1 soft
  * shadow test).  Per view: sun camera B_sun = lam * B'_xy (I - [0 0 s]) with
@@ -341,7 +394,8 @@ ss_status ss_shadow_surrogate(ss_plan *plan, ss_mlp *mlp, const float *w, const 
 #define SS_STAGE_SHADOW_QUERY 11
 #define SS_STAGE_MLP         12   /* surrogate MLP inference (weight copy + fused forward)  */
 #define SS_STAGE_FALLBACK_FLAG 13 /* surrogate fallback: flag points and their sun tiles    */
-#define SS_NUM_STAGES        14
+#define SS_STAGE_NORMAL_LOSS 14   /* depth-gradient normals and the normal-consistency loss */
+#define SS_NUM_STAGES        15
 ss_status ss_plan_set_timing(ss_plan *plan, int32_t enable);
 ss_status ss_plan_read_timing(ss_plan *plan, double *ms, int64_t *launches);
 const char *ss_stage_name(int32_t stage);

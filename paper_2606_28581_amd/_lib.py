@@ -51,6 +51,11 @@ class StepIO(C.Structure):
                 ("d_colc", C.c_void_p), ("d_ambient", C.c_void_p)]
 
 
+class GeomIO(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("depth_scale", C.c_float), ("dist", C.c_void_p),
+                ("aux", C.c_void_p), ("d_dist", C.c_void_p)]
+
+
 class MlpConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("centre", C.c_float * 3), ("inv_half", C.c_float)]
 
@@ -75,6 +80,13 @@ _SIGS = {
                                _P, _P, _P, _P]),
     "ss_backward": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P, _P, _P,
                                 _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ss_forward_geom": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P, _P,
+                                    _P, _P, _P, _P, C.POINTER(GeomIO), _P]),
+    "ss_backward_geom": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P, _P,
+                                     _P, _P, _P, _P, C.POINTER(GeomIO), _P, _P, _P, _P, _P, _P,
+                                     _P, _P, _P, _P, _P]),
+    "ss_normal_loss": (C.c_int32, [_P, C.POINTER(Views), _P, _P, _P, C.c_float, C.c_float, _P,
+                                   _P, _P, _P, _P, _P]),
     "ss_shadow_plain": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P]),
     "ss_debug_binning": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _I64P, _I64P, _P]),
     "ss_debug_sun_cameras": (C.c_int32, [_P, _P, _P]),
@@ -105,7 +117,7 @@ _SIGS = {
                                         C.c_float, _P, _P, _P]),
 }
 
-SS_NUM_STAGES = 14
+SS_NUM_STAGES = 15
 SS_MLP_PARAMS = 16641
 SS_NOALLOC_MAX_POINTS = 16384
 

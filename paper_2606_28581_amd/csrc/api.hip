@@ -58,6 +58,7 @@ struct Layout {
     size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
     size_t sun_depth, bounds, radix_temp, tmask_sun, cmask, cmask_bytes, stat_main, stat_sun;
     size_t inv_order, vis_rank;
+    size_t geom_seeds, geom_cams, geom_parts;
     size_t total;
 };
 
@@ -170,6 +171,13 @@ static void max_tiles(ss_plan *p)
     p->tiles_sun_max = (int32_t)tsn;
 }
 
+static int64_t max_view_pixels(const ss_plan *p)
+{
+    int64_t m = 0;
+    for (int v = 0; v < p->nv; ++v) m = std::max<int64_t>(m, (int64_t)p->W[v] * p->H[v]);
+    return m;
+}
+
 static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
 {
     Layout L{};
@@ -215,6 +223,10 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     // forward -> backward contributor masks of 8x8 tiles (other sizes use the box test)
     L.cmask_bytes = p->st.tile_size == 8 ? cmask_words(cm, p->tiles_main_max) * 8 : 0;
     L.cmask = take(L.cmask_bytes);
+    // normal-consistency loss: per-pixel depth-adjoint seeds, per-view cameras, block sums
+    L.geom_seeds = take((size_t)p->P * 8);
+    L.geom_cams = take(nv * sizeof(GeomCam));
+    L.geom_parts = take((size_t)normal_loss_blocks(max_view_pixels(p)) * nv * 10 * 8);
     L.total = o;
     return L;
 }
@@ -647,7 +659,7 @@ ss_status ss_plan_check(ss_plan *p, int32_t *overflowed, int64_t *main_pairs, in
 static ss_status forward_pass(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
                               float *image, float *albedo_out, float *vis_out, float *depth,
                               float *normal, float *T_final, int32_t *last, hipStream_t st,
-                              uint32_t *order, float *sorted)
+                              uint32_t *order, float *sorted, const DistArgs *dist = nullptr)
 {
     ss_status e;
     p->fwd_valid = false;
@@ -664,7 +676,7 @@ static ss_status forward_pass(ss_plan *p, const ss_surfels *s, const ss_views *v
                                  p->at<uint32_t>(p->L.ranges_main), p->lists_main,
                                  p->at<float>(p->L.rec_main), p->n, rc, v->colC, v->colc,
                                  v->ambient, nullptr, image, albedo_out, vis_out, depth, normal,
-                                 T_final, last, stat, cmask_ptr(p), st));
+                                 T_final, last, stat, cmask_ptr(p), st, dist));
     }
     p->order_main = order;
     p->fwd_valid = true;
@@ -685,12 +697,40 @@ ss_status ss_forward(ss_plan *p, const ss_surfels *s, const ss_views *v, const f
                         reinterpret_cast<hipStream_t>(stream), nullptr, nullptr);
 }
 
-ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
-                      const float *albedo_out, const float *vis_out, const float *T_final,
-                      const int32_t *last, const float *d_image, const float *d_depth,
-                      const float *d_normal, float *d_mean, float *d_t_u, float *d_t_v,
-                      float *d_scale, float *d_opacity, float *d_albedo, float *d_dF,
-                      float *d_colC, float *d_colc, float *d_ambient, ss_stream stream)
+static ss_status geom_args(const ss_plan *p, const ss_geom_io *geom, bool fwd, DistArgs *out)
+{
+    if (!geom || geom->struct_size != sizeof(ss_geom_io))
+        return fail(SS_ERR_INVALID_ARG, "bad ss_geom_io");
+    if (!(geom->depth_scale > 0.f) || !std::isfinite(geom->depth_scale))
+        return fail(SS_ERR_INVALID_ARG, "depth_scale must be positive");
+    if (!geom->aux || (fwd && !geom->dist))
+        return fail(SS_ERR_INVALID_ARG, "geom->aux (and, in the forward, geom->dist) is required");
+    *out = DistArgs{geom->depth_scale, geom->dist, geom->aux, geom->d_dist, p->P};
+    return SS_OK;
+}
+
+ss_status ss_forward_geom(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                          float *image, float *albedo_out, float *vis_out, float *depth,
+                          float *normal, float *T_final, int32_t *last, const ss_geom_io *geom,
+                          ss_stream stream)
+{
+    ss_status e = check_call(p, s, v);
+    if (e != SS_OK) return e;
+    if (!image || !albedo_out || !vis_out || !depth || !normal || !T_final || !last)
+        return fail(SS_ERR_INVALID_ARG, "an output pointer is NULL");
+    DistArgs da;
+    if ((e = geom_args(p, geom, true, &da)) != SS_OK) return e;
+    return forward_pass(p, s, v, vis, image, albedo_out, vis_out, depth, normal, T_final, last,
+                        reinterpret_cast<hipStream_t>(stream), nullptr, nullptr, &da);
+}
+
+static ss_status backward_pass(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                               const float *albedo_out, const float *vis_out, const float *T_final,
+                               const int32_t *last, const float *d_image, const float *d_depth,
+                               const float *d_normal, float *d_mean, float *d_t_u, float *d_t_v,
+                               float *d_scale, float *d_opacity, float *d_albedo, float *d_dF,
+                               float *d_colC, float *d_colc, float *d_ambient, ss_stream stream,
+                               const DistArgs *dist)
 {
     ss_status e = check_call(p, s, v);
     if (e != SS_OK) return e;
@@ -715,7 +755,7 @@ ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
                                  p->lists_main, p->at<float>(L.rec_main), p->n, rc, v->colC,
                                  v->colc, v->ambient, albedo_out, vis_out, T_final, last, d_image,
                                  d_depth, d_normal, recgrad, p->at<float>(L.colour_parts),
-                                 cmask_ptr(p), st));
+                                 cmask_ptr(p), st, dist));
     }
     {
         StageScope scope(p, SS_STAGE_REDUCE, st);
@@ -730,6 +770,59 @@ ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const 
     }
     StageScope scope(p, SS_STAGE_REDUCE, st);
     SS_HIP(launch_dF_reduce(p->at<float>(L.dF_parts), project_bwd_blocks(p->n), p->nv, d_dF, st));
+    return SS_OK;
+}
+
+ss_status ss_backward(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                      const float *albedo_out, const float *vis_out, const float *T_final,
+                      const int32_t *last, const float *d_image, const float *d_depth,
+                      const float *d_normal, float *d_mean, float *d_t_u, float *d_t_v,
+                      float *d_scale, float *d_opacity, float *d_albedo, float *d_dF,
+                      float *d_colC, float *d_colc, float *d_ambient, ss_stream stream)
+{
+    return backward_pass(p, s, v, vis, albedo_out, vis_out, T_final, last, d_image, d_depth,
+                         d_normal, d_mean, d_t_u, d_t_v, d_scale, d_opacity, d_albedo, d_dF,
+                         d_colC, d_colc, d_ambient, stream, nullptr);
+}
+
+ss_status ss_backward_geom(ss_plan *p, const ss_surfels *s, const ss_views *v, const float *vis,
+                           const float *albedo_out, const float *vis_out, const float *T_final,
+                           const int32_t *last, const float *d_image, const float *d_depth,
+                           const float *d_normal, const ss_geom_io *geom, float *d_mean,
+                           float *d_t_u, float *d_t_v, float *d_scale, float *d_opacity,
+                           float *d_albedo, float *d_dF, float *d_colC, float *d_colc,
+                           float *d_ambient, ss_stream stream)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    DistArgs da;
+    ss_status e = geom_args(p, geom, false, &da);
+    if (e != SS_OK) return e;
+    return backward_pass(p, s, v, vis, albedo_out, vis_out, T_final, last, d_image, d_depth,
+                         d_normal, d_mean, d_t_u, d_t_v, d_scale, d_opacity, d_albedo, d_dF,
+                         d_colC, d_colc, d_ambient, stream, &da);
+}
+
+ss_status ss_normal_loss(ss_plan *p, const ss_views *v, const float *depth, const float *T_final,
+                         const float *normal, float weight, float tau, float *loss,
+                         float *normal_d, float *d_depth, float *d_normal, float *d_dF,
+                         ss_stream stream)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->ws) return fail(SS_ERR_STATE, "no workspace bound");
+    if (!v || v->n != p->nv || !v->Fxy) return fail(SS_ERR_INVALID_ARG, "views invalid");
+    if (!depth || !T_final || !normal || !loss || !d_depth || !d_normal)
+        return fail(SS_ERR_INVALID_ARG, "a map, the loss or a gradient pointer is NULL");
+    if (!std::isfinite(weight) || !(tau > 0.f && tau <= 1.f))
+        return fail(SS_ERR_INVALID_ARG, "weight must be finite and tau in (0, 1]");
+    SS_HIP(hipSetDevice(p->ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Layout &L = p->L;
+    StageScope scope(p, SS_STAGE_NORMAL_LOSS, st);
+    SS_HIP(launch_normal_loss(p->at<ViewDesc>(L.views_main), p->nv, max_view_pixels(p), v->Fxy,
+                              v->dF, depth, T_final, normal, weight, tau,
+                              p->at<GeomCam>(L.geom_cams), p->at<float2>(L.geom_seeds),
+                              p->at<double>(L.geom_parts), loss, normal_d, d_depth, d_normal,
+                              d_dF, st));
     return SS_OK;
 }
 
@@ -1242,7 +1335,7 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
 static const char *kStageNames[SS_NUM_STAGES] = {
     "depth_sort", "project", "bin", "raster_fwd", "raster_bwd", "project_bwd", "reduce",
     "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query", "mlp_forward",
-    "fallback_flag"};
+    "fallback_flag", "normal_loss"};
 
 const char *ss_stage_name(int32_t stage)
 {

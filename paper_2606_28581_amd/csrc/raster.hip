@@ -472,7 +472,7 @@ __device__ __forceinline__ uint64_t chunk_mask(float4 head, bool valid, int wx0,
 // builds the mask of records covering its pixel and composites only those, front to
 // back, until its transmittance would drop below T_min; a wave whose 64 pixels all
 // stopped skips the rest, the block stops when all waves have.
-template <int TS, bool DEPTH_ONLY, bool HAS_VIS>
+template <int TS, bool DEPTH_ONLY, bool HAS_VIS, bool DIST>
 __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
@@ -480,7 +480,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     const float *__restrict__ amb, const SunCam *__restrict__ sun, float *__restrict__ image,
     float *__restrict__ Aout, float *__restrict__ Vout, float *__restrict__ Dout,
     float *__restrict__ Nout, float *__restrict__ Tout, int32_t *__restrict__ lastout,
-    unsigned long long *__restrict__ stats, unsigned long long *__restrict__ cmask)
+    unsigned long long *__restrict__ stats, unsigned long long *__restrict__ cmask,
+    DistArgs da)
 {
     constexpr int NT = TS * TS;
     // 8x8 view passes record, per pixel and 64-position word of the tile list, which
@@ -503,6 +504,9 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     constexpr int RS = DEPTH_ONLY ? kSunRecStride4 : kRecStride4;   // record slot
     const float4 *recv = rec + (size_t)v * (size_t)n * RS;
     float Tr = 1.f, aD = 0.f, a0 = 0.f, a1 = 0.f, a2 = 0.f, aV = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    // distortion: accumulated value, reference depth, shifted first and second moments
+    float dacc = 0.f, zref = 0.f, M1 = 0.f, M2 = 0.f;
+    bool has_ref = false;
     int lastpos = 0, ncontrib = 0, neval = 0;
     bool done = !inside;
     const int B = min(rc.batch, NT);
@@ -563,6 +567,16 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
                     n0 = __fmaf_rn(w, r5.x, n0);
                     n1 = __fmaf_rn(w, r5.y, n1);
                     n2 = __fmaf_rn(w, r5.z, n2);
+                }
+                if (DIST) {
+                    // sum_{j<i} w_j (m_i - m_j)^2 = m'(m' (1 - T) - 2 M1) + M2 with m' the
+                    // depth relative to the first contributor
+                    zref = (take && !has_ref) ? z : zref;
+                    has_ref = has_ref || take;
+                    const float mp = (z - zref) * da.ds;
+                    dacc = fmaf(w, fmaf(mp, fmaf(mp, 1.f - Tr, -2.f * M1), M2), dacc);
+                    M1 = fmaf(w, mp, M1);
+                    M2 = fmaf(w * mp, mp, M2);
                 }
                 if (CM) cmc |= take ? 1ull << (jc - c0) : 0ull;
                 Tr = take ? Tn : Tr;
@@ -637,6 +651,12 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     Dout[g] = aD;
     Tout[g] = Tr;
     lastout[g] = lastpos;
+    if (DIST) {
+        da.dist[g] = dacc;
+        da.aux[g] = zref;
+        da.aux[da.P + g] = M1;
+        da.aux[2 * da.P + g] = M2;
+    }
 }
 
 template <int TS, bool DO, bool HV>
@@ -646,11 +666,17 @@ static void launch_fwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const float *colC, const float *colc, const float *amb,
                          const SunCam *sun, float *image, float *A, float *V, float *D,
                          float *N, float *T, int32_t *last, unsigned long long *stats,
-                         unsigned long long *cmask)
+                         unsigned long long *cmask, const DistArgs *dist)
 {
-    hipLaunchKernelGGL((k_raster_fwd<TS, DO, HV>), grid, dim3(TS * TS), lds, st, nv, views,
-                       ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
-                       amb, sun, image, A, V, D, N, T, last, stats, cmask);
+    const DistArgs da = dist ? *dist : DistArgs{0.f, nullptr, nullptr, nullptr, 0};
+    if (!DO && dist)
+        hipLaunchKernelGGL((k_raster_fwd<TS, DO, HV, true>), grid, dim3(TS * TS), lds, st, nv,
+                           views, ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc,
+                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask, da);
+    else
+        hipLaunchKernelGGL((k_raster_fwd<TS, DO, HV, false>), grid, dim3(TS * TS), lds, st, nv,
+                           views, ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc,
+                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask, da);
 }
 
 size_t cmask_words(int64_t pair_cap, int32_t tiles)
@@ -664,7 +690,8 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
                              const RasterConsts &rc, const float *colC, const float *colc,
                              const float *amb, const SunCam *sun, float *image, float *A,
                              float *V, float *D, float *N, float *T, int32_t *last,
-                             unsigned long long *stats, unsigned long long *cmask, hipStream_t st)
+                             unsigned long long *stats, unsigned long long *cmask, hipStream_t st,
+                             const DistArgs *dist)
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
@@ -675,13 +702,13 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
     if (ts == TS_) {                                                                             \
         if (depth_only)                                                                          \
             launch_fwd_t<TS_, true, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
-                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask);\
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask, dist);\
         else if (has_vis)                                                                        \
             launch_fwd_t<TS_, false, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,   \
-                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask);\
+                                           colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask, dist);\
         else                                                                                     \
             launch_fwd_t<TS_, false, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,  \
-                                            colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask);\
+                                            colC, colc, amb, sun, image, A, V, D, N, T, last, stats, cmask, dist);\
     }
     SS_FWD(8) else SS_FWD(16) else SS_FWD(32) else return hipErrorInvalidValue;
 #undef SS_FWD
@@ -836,6 +863,12 @@ struct PixelAdjoint {
     int last;
 };
 
+// Distortion state of a pixel in the backward: upstream gradient, reference depth, total
+// weight 1 - T_final, shifted moments sum w m', sum w m'^2 over all its contributors.
+struct DistPixel {
+    float gDist, zref, At, M1, M2;
+};
+
 template <bool HAS_VIS>
 __device__ __forceinline__ PixelAdjoint pixel_adjoint(
     bool inside, int v, int64_t g, int64_t b3, int64_t P, const float *__restrict__ colC,
@@ -880,14 +913,28 @@ __device__ __forceinline__ PixelAdjoint pixel_adjoint(
     return a;
 }
 
+__device__ __forceinline__ DistPixel pixel_distortion_state(bool inside, int64_t g, float Tr,
+                                                            const DistArgs &da)
+{
+    DistPixel d{0, 0, 0, 0, 0};
+    if (!inside) return d;
+    d.gDist = da.d_dist ? da.d_dist[g] : 0.f;
+    d.zref = da.aux[g];
+    d.M1 = da.aux[da.P + g];
+    d.M2 = da.aux[2 * da.P + g];
+    d.At = 1.f - Tr;
+    return d;
+}
+
 // Gradients of one (record, pixel) pair in the back-to-front walk.  Updates the pixel's
 // transmittance Tr and suffix gS when the pair contributes, returns the 16 record
 // gradient values in gr (zero when it does not).
+template <bool DIST>
 __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, float4 r2,
                                                float4 r3, float4 r4, float4 r5,
-                                               const PixelAdjoint &pa, bool has_vis,
-                                               float two_is2, float alpha_max, float &Tr,
-                                               float &gS, float (&gr)[16])
+                                               const PixelAdjoint &pa, const DistPixel &dp,
+                                               bool has_vis, float two_is2, float alpha_max,
+                                               float ds, float &Tr, float &gS, float (&gr)[16])
 {
     // gradient arithmetic with explicit fused multiply-adds (the discrete decisions -
     // contrib, ub, unclamped - come from eval_pair and the forward's own tests)
@@ -898,10 +945,17 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
     float gf = fmaf(pa.gA0, r4.x, fmaf(pa.gA1, r4.y, fmaf(pa.gA2, r4.z, fmaf(pa.gD, z,
                fmaf(pa.gN0, r5.x, fmaf(pa.gN1, r5.y, pa.gN2 * r5.z))))));
     if (has_vis) gf = fmaf(pa.gV, r4.w, gf);
+    float gDe = pa.gD;
+    if (DIST) {
+        // d dist / d w_k = sum_j w_j (m'_k - m'_j)^2, d dist / d m_k = 2 w_k sum_j w_j (m'_k - m'_j)
+        const float mp = (z - dp.zref) * ds;
+        gf = fmaf(dp.gDist, fmaf(mp, fmaf(mp, dp.At, -2.f * dp.M1), dp.M2), gf);
+        gDe = fmaf(2.f * dp.gDist * ds, fmaf(mp, dp.At, -dp.M1), pa.gD);
+    }
     const float dal = contrib ? fmaf(Tb, gf, -gS * rom) : 0.f;
     gS = fmaf(w, gf, gS);
     Tr = contrib ? Tb : Tr;
-    const float dz = w * pa.gD;
+    const float dz = w * gDe;
     gr[G_AR] = w * pa.gA0; gr[G_AG] = w * pa.gA1; gr[G_AB] = w * pa.gA2;
     gr[G_NX] = w * pa.gN0; gr[G_NY] = w * pa.gN1; gr[G_NZ] = w * pa.gN2;
     gr[G_Z0] = dz;
@@ -941,8 +995,8 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
 // lane, so one instruction carries the sums of up to four records.
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
-template <int TS, bool HAS_VIS>
-__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 6 : 4))) void k_raster_bwd(
+template <int TS, bool HAS_VIS, bool DIST>
+__global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 5 : 4))) void k_raster_bwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
     RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
@@ -950,7 +1004,8 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     const float *__restrict__ Vin, const float *__restrict__ Tin,
     const int32_t *__restrict__ lastin, const float *__restrict__ dI,
     const float *__restrict__ dD, const float *__restrict__ dN, float *__restrict__ recgrad,
-    float *__restrict__ colour_partials, const unsigned long long *__restrict__ cmask)
+    float *__restrict__ colour_partials, const unsigned long long *__restrict__ cmask,
+    DistArgs da)
 {
     constexpr int NT = TS * TS;
     constexpr int NW = NT / 64;
@@ -983,6 +1038,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     float cg[16];
     const PixelAdjoint pa = pixel_adjoint<HAS_VIS>(inside, v, g, b3, P, colC, colc, amb, Ain, Vin,
                                                    Tin, lastin, dI, dD, dN, cg);
+    const DistPixel dp = DIST ? pixel_distortion_state(inside, g, pa.Tr, da) : DistPixel{0, 0, 0, 0, 0};
     float Tr = pa.Tr;
     const int mylast = pa.last;
     {
@@ -1101,8 +1157,8 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 }
                 const bool contrib = act && bb + j < mylast && fwd_took;
                 float gr[16];
-                pair_gradients(e, contrib, r2, r3, r4, r5, pa, HAS_VIS, two_is2, rc.alpha_max, Tr,
-                               gS, gr);
+                pair_gradients<DIST>(e, contrib, r2, r3, r4, r5, pa, dp, HAS_VIS, two_is2,
+                                     rc.alpha_max, da.ds, Tr, gS, gr);
                 const uint64_t cb = __ballot(contrib);
                 if (cb == 0) continue;
                 const float sum = row_transpose_reduce16(gr, lane);
@@ -1122,11 +1178,17 @@ static void launch_bwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const float *colC, const float *colc, const float *amb,
                          const float *A, const float *V, const float *T, const int32_t *last,
                          const float *dI, const float *dD, const float *dN, float *recgrad,
-                         float *cp, const unsigned long long *cmask)
+                         float *cp, const unsigned long long *cmask, const DistArgs *dist)
 {
-    hipLaunchKernelGGL((k_raster_bwd<TS, HV>), grid, dim3(TS * TS), lds, st, nv, views, ranges,
-                       lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc, amb, A,
-                       V, T, last, dI, dD, dN, recgrad, cp, cmask);
+    const DistArgs da = dist ? *dist : DistArgs{0.f, nullptr, nullptr, nullptr, 0};
+    if (dist)
+        hipLaunchKernelGGL((k_raster_bwd<TS, HV, true>), grid, dim3(TS * TS), lds, st, nv, views,
+                           ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
+                           amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+    else
+        hipLaunchKernelGGL((k_raster_bwd<TS, HV, false>), grid, dim3(TS * TS), lds, st, nv, views,
+                           ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
+                           amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
 }
 
 hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
@@ -1137,7 +1199,7 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
                              const float *T, const int32_t *last, const float *dI,
                              const float *dD, const float *dN, float *recgrad,
                              float *colour_partials, const unsigned long long *cmask,
-                             hipStream_t st)
+                             hipStream_t st, const DistArgs *dist)
 {
     if (total_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)total_tiles);
@@ -1148,11 +1210,11 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
         if (has_vis)                                                                         \
             launch_bwd_t<TS_, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,      \
                                     colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad,     \
-                                    colour_partials, cmask);                                 \
+                                    colour_partials, cmask, dist);                                 \
         else                                                                                 \
             launch_bwd_t<TS_, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc,     \
                                      colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad,    \
-                                     colour_partials, cmask);                                \
+                                     colour_partials, cmask, dist);                                \
     }
     SS_BWD(8) else SS_BWD(16) else SS_BWD(32) else return hipErrorInvalidValue;
 #undef SS_BWD

@@ -66,6 +66,14 @@ struct SunCam {
     double pad[7];
 };
 
+// Per-view back-projection of the depth-normal loss: Minv = [B_x; B_y; (0,0,-1)]^-1
+// (row-major) and the view direction d = B_x x B_y with d_z < 0.
+struct GeomCam {
+    double Minv[9];
+    double d[3];
+    double pad[4];
+};
+
 struct RasterConsts {
     float alpha_min, alpha_max, T_min, inv_s2;
     int32_t lowpass_mode;
@@ -73,6 +81,20 @@ struct RasterConsts {
     float esm_c, esm_bias;
     float two_inv_s2;   // 2 inv_s2, a kernel argument so that loops read it from an SGPR
     double alpha_min_d, sigma_d, det_rel_eps_d;
+};
+
+// Depth-distortion channel of the view raster (the 2DGS squared form of the distortion
+// loss): per pixel the forward writes dist = sum over contributor pairs of
+// w_i w_j (m_i - m_j)^2, m = z * ds, and saves aux = (z_ref, M1, M2): the depth of the
+// pixel's first contributor and sum w m', sum w m'^2 of m' = (z - z_ref) * ds (shifted
+// so the moments do not cancel); the backward reads aux and the upstream d_dist.
+// Planar over all pixels of all views: aux[k * P + g].
+struct DistArgs {
+    float ds;
+    float *dist;
+    float *aux;
+    const float *d_dist;
+    int64_t P;
 };
 
 struct SurfelPtrs {
@@ -166,7 +188,8 @@ hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t tota
                              const RasterConsts &rc, const float *colC, const float *colc,
                              const float *amb, const SunCam *sun, float *image, float *A,
                              float *V, float *D, float *N, float *T, int32_t *last,
-                             unsigned long long *stats, unsigned long long *cmask, hipStream_t st);
+                             unsigned long long *stats, unsigned long long *cmask, hipStream_t st,
+                             const DistArgs *dist = nullptr);
 hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
                              const ViewDesc *views, const uint32_t *ranges,
                              const uint32_t *lists, const float *rec, int64_t n,
@@ -175,7 +198,7 @@ hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t 
                              const float *T, const int32_t *last, const float *dI,
                              const float *dD, const float *dN, float *recgrad,
                              float *colour_partials, const unsigned long long *cmask,
-                             hipStream_t st);
+                             hipStream_t st, const DistArgs *dist = nullptr);
 // Contributor masks (8x8 tiles): for tile t with list start s, word w of pixel (lane) l is
 // cmask[(s / 64 + t + w) * 64 + l], bit b set iff list position 64 w + b was composited;
 // the ranges of different tiles are disjoint, so (pairs / 64 + tiles + 1) * 64 words suffice.
@@ -200,6 +223,16 @@ hipError_t launch_unpermute_tiles(const uint32_t *order, int64_t n, int32_t nv, 
 hipError_t launch_map_through(const uint32_t *order, int64_t n_order,
                               const unsigned long long *n_dev, int64_t cap, const uint32_t *in,
                               uint32_t *out, hipStream_t st);
+
+// geom.hip: depth-gradient normals and the normal-consistency loss over all views.
+// seeds: one float2 per pixel; partials: normal_loss_blocks(max view pixels) * nv * 10
+// doubles; cams: nv entries.  loss [nv] is written; d_depth, d_normal and d_dF are added to.
+int normal_loss_blocks(int64_t max_view_pixels);
+hipError_t launch_normal_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pixels,
+                              const float *Fxy, const float *dF, const float *D, const float *T,
+                              const float *Nr, float weight, float tau, GeomCam *cams,
+                              float2 *seeds, double *partials, float *loss, float *Nd_out,
+                              float *d_depth, float *d_normal, float *d_dF, hipStream_t st);
 
 // shadow.hip
 int bounds_blocks(int64_t n);

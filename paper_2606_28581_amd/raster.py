@@ -16,6 +16,14 @@ from . import _lib
 from ._lib import RasterSettings, StepIO, Surfels, Views, call
 
 
+def geom_io(depth_scale: float, dist=None, aux=None, d_dist=None):
+    g = _lib.GeomIO()
+    g.struct_size = C.sizeof(_lib.GeomIO)
+    g.depth_scale = float(depth_scale)
+    g.dist, g.aux, g.d_dist = _ptr(dist), _ptr(aux), _ptr(d_dist)
+    return g
+
+
 def default_settings(**overrides) -> RasterSettings:
     s = RasterSettings()
     _lib.load().ss_default_settings(C.byref(s))
@@ -166,18 +174,29 @@ class Plan:
 
     # ------------------------------------------------------------------ raw calls
     def forward(self, s: SurfelTensors, v: ViewTensors, vis: Optional[torch.Tensor] = None,
-                out: Optional[Dict[str, torch.Tensor]] = None, check: bool = True):
+                out: Optional[Dict[str, torch.Tensor]] = None, check: bool = True,
+                depth_scale: Optional[float] = None):
+        """ss_forward; with depth_scale, ss_forward_geom: out also holds the per-pixel
+        depth distortion 'dist' and the state 'dist_aux' its backward needs."""
         P = v.pixels
         dev = s.mean.device
         if out is None:
             f = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=dev)
             out = dict(image=f(3 * P), albedo=f(3 * P), vis=f(P), depth=f(P), normal=f(3 * P),
                        T=f(P), last=torch.empty(P, dtype=torch.int32, device=dev))
+        if depth_scale is not None and "dist" not in out:
+            out["dist"] = torch.empty(P, dtype=torch.float32, device=dev)
+            out["dist_aux"] = torch.empty(3 * P, dtype=torch.float32, device=dev)
         for attempt in range(3):
             sc, vc = s.c(), v.c()
-            call("ss_forward", self.handle, C.byref(sc), C.byref(vc), _ptr(vis),
-                 _ptr(out["image"]), _ptr(out["albedo"]), _ptr(out["vis"]), _ptr(out["depth"]),
-                 _ptr(out["normal"]), _ptr(out["T"]), _ptr(out["last"]), _stream())
+            args = (self.handle, C.byref(sc), C.byref(vc), _ptr(vis),
+                    _ptr(out["image"]), _ptr(out["albedo"]), _ptr(out["vis"]), _ptr(out["depth"]),
+                    _ptr(out["normal"]), _ptr(out["T"]), _ptr(out["last"]))
+            if depth_scale is None:
+                call("ss_forward", *args, _stream())
+            else:
+                gio = geom_io(depth_scale, out["dist"], out["dist_aux"])
+                call("ss_forward_geom", *args, C.byref(gio), _stream())
             if not check:
                 break
             over, m, _ = self.check()
@@ -188,7 +207,10 @@ class Plan:
         return out
 
     def backward(self, s: SurfelTensors, v: ViewTensors, fwd: Dict[str, torch.Tensor],
-                 d_image=None, d_depth=None, d_normal=None, vis=None, grads=None):
+                 d_image=None, d_depth=None, d_normal=None, vis=None, grads=None,
+                 depth_scale: Optional[float] = None, d_dist=None):
+        """ss_backward; with depth_scale, ss_backward_geom (adds the adjoint of the depth
+        distortion for the upstream gradient d_dist, from the forward's 'dist_aux')."""
         n, nv = s.mean.shape[0], len(v.width)
         dev = s.mean.device
         if grads is None:
@@ -197,12 +219,37 @@ class Plan:
                          albedo=z(n, 3), dF=z(nv, 2, 4), colC=z(nv, 3, 3), colc=z(nv, 3),
                          ambient=z(nv, 3))
         sc, vc = s.c(), v.c()
-        call("ss_backward", self.handle, C.byref(sc), C.byref(vc), _ptr(vis),
-             _ptr(fwd["albedo"]), _ptr(fwd["vis"]), _ptr(fwd["T"]), _ptr(fwd["last"]),
-             _ptr(d_image), _ptr(d_depth), _ptr(d_normal),
-             *[_ptr(grads[k]) for k in ("mean", "t_u", "t_v", "scale", "opacity", "albedo", "dF",
-                                        "colC", "colc", "ambient")], _stream())
+        head = (self.handle, C.byref(sc), C.byref(vc), _ptr(vis),
+                _ptr(fwd["albedo"]), _ptr(fwd["vis"]), _ptr(fwd["T"]), _ptr(fwd["last"]),
+                _ptr(d_image), _ptr(d_depth), _ptr(d_normal))
+        tail = [_ptr(grads[k]) for k in ("mean", "t_u", "t_v", "scale", "opacity", "albedo", "dF",
+                                         "colC", "colc", "ambient")]
+        if depth_scale is None:
+            call("ss_backward", *head, *tail, _stream())
+        else:
+            gio = geom_io(depth_scale, None, fwd["dist_aux"], d_dist)
+            call("ss_backward_geom", *head, C.byref(gio), *tail, _stream())
         return grads
+
+    def normal_loss(self, v: ViewTensors, fwd: Dict[str, torch.Tensor], weight: float = 1.0,
+                    tau: float = 0.5, d_depth=None, d_normal=None, d_dF=None,
+                    normal_d: bool = False):
+        """ss_normal_loss on the forward's depth, T and normal maps.  Returns (loss per
+        view, d_depth, d_normal, d_dF, depth normals or None); the gradients are added to
+        the given buffers (zeros when None)."""
+        P, nv = v.pixels, len(v.width)
+        dev = fwd["depth"].device
+        z = lambda *shape: torch.zeros(*shape, dtype=torch.float32, device=dev)
+        d_depth = z(P) if d_depth is None else d_depth
+        d_normal = z(3 * P) if d_normal is None else d_normal
+        d_dF = z(nv, 2, 4) if d_dF is None else d_dF
+        loss = torch.empty(nv, dtype=torch.float32, device=dev)
+        Nd = torch.empty(3 * P, dtype=torch.float32, device=dev) if normal_d else None
+        vc = v.c()
+        call("ss_normal_loss", self.handle, C.byref(vc), _ptr(fwd["depth"]), _ptr(fwd["T"]),
+             _ptr(fwd["normal"]), float(weight), float(tau), _ptr(loss), _ptr(Nd),
+             _ptr(d_depth), _ptr(d_normal), _ptr(d_dF), _stream())
+        return loss, d_depth, d_normal, d_dF, Nd
 
     def shadow(self, s: SurfelTensors, v: ViewTensors, vis_out=None, sun_depth=None,
                check: bool = True):
