@@ -234,6 +234,60 @@ ss_status ss_normal_loss(ss_plan *plan, const ss_views *v, const float *depth,
                          float *loss, float *normal_d, float *d_depth, float *d_normal,
                          float *d_dF, ss_stream stream);
 
+/* ------------------------------------------------------------ training step
+ * The optimiser around the rasterizer (Supp. B "Experimental Settings": Adam with per-group
+ * learning rates, L1 image loss, camera-delta optimisation from a start step).
+ * Raw surfel parameters, SS_RAW_FLOATS per surfel, row-major [n, 13]: mean (3, metres),
+ * log s_u, log s_v, opacity logit, rotation quaternion (w, x, y, z) of any non-zero norm,
+ * albedo (3).  Activated (the ss_surfels arrays): scale = exp(log scale), opacity =
+ * sigmoid(logit), t_u and t_v = the first two columns of the rotation of q / |q| (the
+ * third is the normal, Sec. 3.1). */
+#define SS_RAW_FLOATS 13
+typedef struct ss_adam_config {
+    uint32_t struct_size;   /* sizeof(ss_adam_config)                                   */
+    float lr_mean, lr_scale, lr_opacity, lr_quat, lr_albedo;   /* surfel groups           */
+    float lr_dF;            /* camera delta                                             */
+    float lr_colour;        /* colour gain C and bias c (the ambient term is not trained) */
+    float beta1, beta2, eps;
+    int32_t camera_start;   /* the camera-delta group is updated from this step on; its
+                               bias correction counts its own steps, t - camera_start + 1 */
+} ss_adam_config;
+
+/* Activated surfel arrays ([n,3] mean, t_u, t_v, albedo, [n,2] scale, [n] opacity) from
+ * the raw parameters. */
+ss_status ss_surfel_activate(int64_t n, const float *raw, float *mean, float *t_u, float *t_v,
+                             float *scale, float *opacity, float *albedo, ss_stream stream);
+/* Raw parameters [n, 13] from activated arrays (t_u, t_v orthonormal; scale > 0;
+ * opacity in (0, 1)): log scale, logit opacity, and a quaternion of the frame
+ * [t_u, t_v, t_u x t_v] (its sign is arbitrary: q and -q give the same frame). */
+ss_status ss_surfel_raw(int64_t n, const float *mean, const float *t_u, const float *t_v,
+                        const float *scale, const float *opacity, const float *albedo, float *raw,
+                        ss_stream stream);
+/* One Adam step (t = step >= 1, bias-corrected: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)) on the raw parameters, with
+ * their gradient obtained from the gradients of the activated arrays (d_*, as written by
+ * ss_backward); then the activated arrays are rewritten from the new raw parameters.
+ * raw, m, v: [n, 13] (m, v start at zero). */
+ss_status ss_adam_surfels(int64_t n, float *raw, float *m, float *v, const float *d_mean,
+                          const float *d_t_u, const float *d_t_v, const float *d_scale,
+                          const float *d_opacity, const float *d_albedo,
+                          const ss_adam_config *cfg, int32_t step, float *mean, float *t_u,
+                          float *t_v, float *scale, float *opacity, float *albedo,
+                          ss_stream stream);
+/* Adam on the per-view terms: dF [nv,2,4] (from cfg->camera_start on), colC [nv,3,3] and
+ * colc [nv,3]; any group may be NULL (not trained); m_*, v_* have the group's shape.  The
+ * camera-delta gradient is d_dF + d_dF_extra (d_dF_extra may be NULL; e.g. the normal-
+ * consistency term's, which ss_normal_loss adds to its own buffer). */
+ss_status ss_adam_views(int32_t nv, float *dF, float *m_dF, float *v_dF, const float *d_dF,
+                        const float *d_dF_extra, float *colC, float *m_colC, float *v_colC, const float *d_colC,
+                        float *colc, float *m_colc, float *v_colc, const float *d_colc,
+                        const ss_adam_config *cfg, int32_t step, ss_stream stream);
+/* L1 image loss of every view of the plan: loss[v] = weight / (3 P_v) * sum over its pixels
+ * and channels of |image - target| (planar layout as ss_forward's image), and
+ * d_image = weight sign(image - target) / (3 P_v) (written; sign(0) = 0). */
+ss_status ss_image_loss_l1(ss_plan *plan, const float *image, const float *target, float weight,
+                           float *loss, float *d_image, ss_stream stream);
+
 /* -------------------------------------------------------------- shadow pass
  * Geometric sun-view shadow map (Sec. 3.3 Eq. sun_camera_Bxy, Supp. A; Sec. 3.1 soft
  * shadow test).  Per view: sun camera B_sun = lam * B'_xy (I - [0 0 s]) with
@@ -395,7 +449,8 @@ ss_status ss_shadow_surrogate(ss_plan *plan, ss_mlp *mlp, const float *w, const 
 #define SS_STAGE_MLP         12   /* surrogate MLP inference (weight copy + fused forward)  */
 #define SS_STAGE_FALLBACK_FLAG 13 /* surrogate fallback: flag points and their sun tiles    */
 #define SS_STAGE_NORMAL_LOSS 14   /* depth-gradient normals and the normal-consistency loss */
-#define SS_NUM_STAGES        15
+#define SS_STAGE_IMAGE_LOSS  15   /* L1 image loss and its gradient                         */
+#define SS_NUM_STAGES        16
 ss_status ss_plan_set_timing(ss_plan *plan, int32_t enable);
 ss_status ss_plan_read_timing(ss_plan *plan, double *ms, int64_t *launches);
 const char *ss_stage_name(int32_t stage);

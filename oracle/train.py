@@ -17,7 +17,9 @@ the parameterisation):
   gradient weight * sign(I - I*) / (3 P) (sign(0) = 0);
 * Adam with bias correction, step t counted from 1: m = b1 m + (1 - b1) g,
   v = b2 v + (1 - b2) g^2, theta -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps);
-  the camera-delta group is not updated (nor are its moments) before `camera_start`.
+  the camera-delta group is not updated (nor are its moments) before `camera_start`,
+  and its bias correction counts its own steps, t - camera_start + 1; the colour gain
+  and bias use lr_colour from the first step, the ambient term is not trained.
 """
 from __future__ import annotations
 

@@ -56,6 +56,13 @@ class GeomIO(C.Structure):
                 ("aux", C.c_void_p), ("d_dist", C.c_void_p)]
 
 
+class AdamConfig(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("lr_mean", C.c_float), ("lr_scale", C.c_float),
+                ("lr_opacity", C.c_float), ("lr_quat", C.c_float), ("lr_albedo", C.c_float),
+                ("lr_dF", C.c_float), ("lr_colour", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("camera_start", C.c_int32)]
+
+
 class MlpConfig(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("centre", C.c_float * 3), ("inv_half", C.c_float)]
 
@@ -87,6 +94,13 @@ _SIGS = {
                                      _P, _P, _P, _P, _P]),
     "ss_normal_loss": (C.c_int32, [_P, C.POINTER(Views), _P, _P, _P, C.c_float, C.c_float, _P,
                                    _P, _P, _P, _P, _P]),
+    "ss_surfel_activate": (C.c_int32, [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ss_surfel_raw": (C.c_int32, [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ss_adam_surfels": (C.c_int32, [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                    C.POINTER(AdamConfig), C.c_int32, _P, _P, _P, _P, _P, _P, _P]),
+    "ss_adam_views": (C.c_int32, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                  C.POINTER(AdamConfig), C.c_int32, _P]),
+    "ss_image_loss_l1": (C.c_int32, [_P, _P, _P, C.c_float, _P, _P, _P]),
     "ss_shadow_plain": (C.c_int32, [_P, C.POINTER(Surfels), C.POINTER(Views), _P, _P, _P]),
     "ss_debug_binning": (C.c_int32, [_P, C.c_int32, _P, _P, _P, _P, _P, _I64P, _I64P, _P]),
     "ss_debug_sun_cameras": (C.c_int32, [_P, _P, _P]),
@@ -117,7 +131,8 @@ _SIGS = {
                                         C.c_float, _P, _P, _P]),
 }
 
-SS_NUM_STAGES = 15
+SS_NUM_STAGES = 16
+SS_RAW_FLOATS = 13
 SS_MLP_PARAMS = 16641
 SS_NOALLOC_MAX_POINTS = 16384
 

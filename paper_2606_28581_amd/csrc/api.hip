@@ -226,7 +226,8 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     // normal-consistency loss: per-pixel depth-adjoint seeds, per-view cameras, block sums
     L.geom_seeds = take((size_t)p->P * 8);
     L.geom_cams = take(nv * sizeof(GeomCam));
-    L.geom_parts = take((size_t)normal_loss_blocks(max_view_pixels(p)) * nv * 10 * 8);
+    L.geom_parts = take((size_t)std::max(normal_loss_blocks(max_view_pixels(p)) * 10,
+                                         l1_blocks(max_view_pixels(p))) * nv * 8);
     L.total = o;
     return L;
 }
@@ -1332,10 +1333,100 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
     return SS_OK;
 }
 
+static ss_status adam_args(const ss_adam_config *c, AdamArgs *a)
+{
+    if (!c || c->struct_size != sizeof(ss_adam_config)) return fail(SS_ERR_INVALID_ARG, "bad ss_adam_config");
+    const float lr[7] = {c->lr_mean, c->lr_scale, c->lr_opacity, c->lr_quat, c->lr_albedo, c->lr_dF,
+                         c->lr_colour};
+    for (int k = 0; k < 7; ++k) {
+        if (!(lr[k] >= 0.f) || !std::isfinite(lr[k])) return fail(SS_ERR_INVALID_ARG, "learning rates must be >= 0");
+        a->lr[k] = lr[k];
+    }
+    if (!(c->beta1 >= 0.f && c->beta1 < 1.f) || !(c->beta2 >= 0.f && c->beta2 < 1.f) || !(c->eps >= 0.f))
+        return fail(SS_ERR_INVALID_ARG, "Adam betas must be in [0, 1) and eps >= 0");
+    a->beta1 = c->beta1; a->beta2 = c->beta2; a->eps = c->eps;
+    a->camera_start = c->camera_start;
+    return SS_OK;
+}
+
+ss_status ss_surfel_activate(int64_t n, const float *raw, float *mean, float *t_u, float *t_v,
+                             float *scale, float *opacity, float *albedo, ss_stream stream)
+{
+    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && (!raw || !mean || !t_u || !t_v || !scale || !opacity || !albedo))
+        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    SS_HIP(launch_surfel_activate(n, raw, mean, t_u, t_v, scale, opacity, albedo,
+                                  reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
+ss_status ss_surfel_raw(int64_t n, const float *mean, const float *t_u, const float *t_v,
+                        const float *scale, const float *opacity, const float *albedo, float *raw,
+                        ss_stream stream)
+{
+    if (n < 0) return fail(SS_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && (!raw || !mean || !t_u || !t_v || !scale || !opacity || !albedo))
+        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    SS_HIP(launch_surfel_raw(n, mean, t_u, t_v, scale, opacity, albedo, raw,
+                             reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
+ss_status ss_adam_surfels(int64_t n, float *raw, float *m, float *v, const float *d_mean,
+                          const float *d_t_u, const float *d_t_v, const float *d_scale,
+                          const float *d_opacity, const float *d_albedo,
+                          const ss_adam_config *cfg, int32_t step, float *mean, float *t_u,
+                          float *t_v, float *scale, float *opacity, float *albedo, ss_stream stream)
+{
+    AdamArgs a;
+    ss_status e = adam_args(cfg, &a);
+    if (e != SS_OK) return e;
+    if (n < 0 || step < 1) return fail(SS_ERR_INVALID_ARG, "n < 0 or step < 1");
+    if (n > 0 && (!raw || !m || !v || !d_mean || !d_t_u || !d_t_v || !d_scale || !d_opacity ||
+                  !d_albedo || !mean || !t_u || !t_v || !scale || !opacity || !albedo))
+        return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    SS_HIP(launch_adam_surfels(n, raw, m, v, d_mean, d_t_u, d_t_v, d_scale, d_opacity, d_albedo, a,
+                               step, mean, t_u, t_v, scale, opacity, albedo,
+                               reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
+ss_status ss_adam_views(int32_t nv, float *dF, float *m_dF, float *v_dF, const float *d_dF,
+                        const float *d_dF_extra, float *colC, float *m_colC, float *v_colC, const float *d_colC,
+                        float *colc, float *m_colc, float *v_colc, const float *d_colc,
+                        const ss_adam_config *cfg, int32_t step, ss_stream stream)
+{
+    AdamArgs a;
+    ss_status e = adam_args(cfg, &a);
+    if (e != SS_OK) return e;
+    if (nv < 0 || step < 1) return fail(SS_ERR_INVALID_ARG, "nv < 0 or step < 1");
+    if ((dF && (!m_dF || !v_dF || !d_dF)) || (colC && (!m_colC || !v_colC || !d_colC)) ||
+        (colc && (!m_colc || !v_colc || !d_colc)))
+        return fail(SS_ERR_INVALID_ARG, "a parameter group lacks its moments or gradient");
+    SS_HIP(launch_adam_views(nv, dF, m_dF, v_dF, d_dF, d_dF_extra, colC, m_colC, v_colC, d_colC, colc, m_colc,
+                             v_colc, d_colc, a, step, reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
+ss_status ss_image_loss_l1(ss_plan *p, const float *image, const float *target, float weight,
+                           float *loss, float *d_image, ss_stream stream)
+{
+    if (!p) return fail(SS_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->ws) return fail(SS_ERR_STATE, "no workspace bound");
+    if (!image || !target || !loss || !d_image) return fail(SS_ERR_INVALID_ARG, "NULL pointer");
+    if (!std::isfinite(weight)) return fail(SS_ERR_INVALID_ARG, "weight must be finite");
+    SS_HIP(hipSetDevice(p->ctx->device));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    StageScope scope(p, SS_STAGE_IMAGE_LOSS, st);
+    SS_HIP(launch_l1_loss(p->at<ViewDesc>(p->L.views_main), p->nv, max_view_pixels(p), image, target,
+                          weight, d_image, p->at<double>(p->L.geom_parts), loss, st));
+    return SS_OK;
+}
+
 static const char *kStageNames[SS_NUM_STAGES] = {
     "depth_sort", "project", "bin", "raster_fwd", "raster_bwd", "project_bwd", "reduce",
     "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query", "mlp_forward",
-    "fallback_flag", "normal_loss"};
+    "fallback_flag", "normal_loss", "image_loss"};
 
 const char *ss_stage_name(int32_t stage)
 {

@@ -234,6 +234,32 @@ hipError_t launch_normal_loss(const ViewDesc *views, int32_t nv, int64_t max_vie
                               float2 *seeds, double *partials, float *loss, float *Nd_out,
                               float *d_depth, float *d_normal, float *d_dF, hipStream_t st);
 
+// train.hip: surfel activations, fused activation adjoint + Adam, per-view Adam, L1 loss.
+// lr: mean, scale, opacity, quaternion, albedo, camera delta, colour.
+struct AdamArgs {
+    float lr[7];
+    float beta1, beta2, eps;
+    int32_t camera_start;
+};
+hipError_t launch_surfel_activate(int64_t n, const float *raw, float *mean, float *tu, float *tv,
+                                  float *scale, float *opacity, float *albedo, hipStream_t st);
+hipError_t launch_surfel_raw(int64_t n, const float *mean, const float *tu, const float *tv,
+                             const float *scale, const float *opacity, const float *albedo,
+                             float *raw, hipStream_t st);
+hipError_t launch_adam_surfels(int64_t n, float *raw, float *m, float *v, const float *g_mean,
+                               const float *g_tu, const float *g_tv, const float *g_scale,
+                               const float *g_opacity, const float *g_albedo, const AdamArgs &a,
+                               int32_t step, float *mean, float *tu, float *tv, float *scale,
+                               float *opacity, float *albedo, hipStream_t st);
+hipError_t launch_adam_views(int32_t nv, float *dF, float *m_dF, float *v_dF, const float *g_dF,
+                             const float *g_dF2, float *colC, float *m_C, float *v_C, const float *g_C, float *colc,
+                             float *m_c, float *v_c, const float *g_c, const AdamArgs &a,
+                             int32_t step, hipStream_t st);
+int l1_blocks(int64_t max_view_pixels);
+hipError_t launch_l1_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pixels,
+                          const float *img, const float *tgt, float weight, float *d_img,
+                          double *partials, float *loss, hipStream_t st);
+
 // shadow.hip
 int bounds_blocks(int64_t n);
 hipError_t launch_sun_cameras(const float *mean, int64_t n, int32_t nv, const float *Fxy,
