@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training / evaluating the learned shadow surrogate")
     ap.add_argument("--surrogate-epochs", type=int, default=30)
+    ap.add_argument("--no-camera", action="store_true",
+                    help="skip the camera-robustness experiment")
     ap.add_argument("--no-c5", action="store_true",
                     help="skip the training-step-scale run (5M surfels, 50 views of 2048^2)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -215,12 +217,16 @@ def surrogate_eval(ctx, args):
 
 
 def training_scale(args, tile=None, batch=None):
-    """Full training-step scale: 5M surfels on a 2x2 km city, 50 views of 2048^2.  Per step
-    the learned shadow surrogate (plain-pass fallback for |p - 0.5| < 0.1) gives every
-    view's surfel visibility, then forward and backward of all views with colour
-    correction and camera-delta gradients.  The surrogate is first trained with the
-    library's kernels on this scene's own plain-pass labels.  Reports steps/s, Mpix/s and
-    peak device memory."""
+    """Full training step at scale: 5M surfels on a 2x2 km city, 50 views of 2048^2.  Per
+    step the learned shadow surrogate (plain-pass fallback for |p - 0.5| < 0.1) gives
+    every view's surfel visibility; then the forward of all views with colour correction,
+    camera deltas and the depth-distortion channel, the L1 image loss (0.8) against a
+    fixed target, the depth-normal consistency loss (0.05) and the distortion (0.05), the
+    backward, and Adam over the surfels, camera deltas and colour terms (the paper's loss
+    weights; learning rates small enough that the pair count stays within the plan's
+    capacity over the timed steps).  The surrogate is first trained with the library's
+    kernels on this scene's own plain-pass labels.  Reports steps/s, Mpix/s and peak
+    device memory."""
     import numpy as np
     import torch
     import synth
@@ -246,23 +252,19 @@ def training_scale(args, tile=None, batch=None):
     w, tr = st.train(lab, net, cfg, log=log)
     del lab
     torch.cuda.empty_cache()
+    from paper_2606_28581_amd import train as trn
     dev = "cuda:0"
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(spec.seed)
-    dI = torch.randn(3 * P, generator=gen, device=dev)
-    dD = torch.randn(P, generator=gen, device=dev)
-    dN = torch.randn(3 * P, generator=gen, device=dev)
-    f = lambda *shape: torch.empty(*shape, dtype=torch.float32, device=dev)
-    vis = f(V, N)
-    out = dict(image=f(3 * P), albedo=f(3 * P), vis=f(P), depth=f(P), normal=f(3 * P), T=f(P),
-               last=torch.empty(P, dtype=torch.int32, device=dev))
-    grads = dict(mean=f(N, 3), t_u=f(N, 3), t_v=f(N, 3), scale=f(N, 2), opacity=f(N),
-                 albedo=f(N, 3), dF=f(V, 2, 4), colC=f(V, 3, 3), colc=f(V, 3), ambient=f(V, 3))
+    vis = torch.empty(V, N, dtype=torch.float32, device=dev)
+    shade = lambda: sg.shadow_surrogate(plan, net, w, surf, views, band=0.1, vis_out=vis)
+    # target: the first render with 10 % less light (set up once, outside the timing)
+    target = (plan.forward(surf, views, shade())["image"] * 0.9).contiguous()
+    cfg = trn.adam_config(lr_mean=1e-3, lr_dF=1e-5, camera_start=1)
+    trainer = trn.Trainer(plan, surf, views, target, depth_scale=2.0 / spec.extent, cfg=cfg,
+                          vis=shade)
+    trainer.check = False      # the overflow flag is read once after the timed steps
 
     def step():
-        sg.shadow_surrogate(plan, net, w, surf, views, band=0.1, vis_out=vis)
-        plan.forward(surf, views, vis, out=out, check=False)
-        plan.backward(surf, views, out, dI, dD, dN, vis=vis, grads=grads)
+        trainer.step()
 
     for i in range(args.warmup):
         step()
@@ -303,7 +305,10 @@ def training_scale(args, tile=None, batch=None):
         "config": {"workload": spec.name, "surfels": N, "views": V, "pixels": P,
                    "tile": settings.tile_size, "batch_depth": settings.batch_depth,
                    "shadow": "MLP surrogate, plain-pass fallback |p-0.5|<0.1",
+                   "step": "surrogate shadows + forward (with distortion) + L1 + normal "
+                           "consistency + backward + Adam (surfels, camera deltas, colour)",
                    "launch": "eager", "parallelism": "single GPU"},
+        "loss_l1_last": float(trainer.loss_l1.sum()),
         "peak_hbm_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
         "pairs": {"main": K, "sun_full": Ks},
         "surrogate": {"fallback_fraction": round(fallback, 5), "training": tr},
@@ -475,6 +480,16 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host")
         result["cpu_baseline"] = cpu_baseline(scene, args.cpu_pixels)
+    if not args.no_camera and args.config == 3:
+        log("[bench] camera-robustness experiment (c1 scene, 4 views of 256^2)")
+        from paper_2606_28581_amd import experiments
+        t0 = time.time()
+        csc = synth.make_scene(synth.config(1, views=[(256, 256)] * 4))
+        rows = experiments.camera_robustness(csc, steps=300, ctx=ctx, log=log)
+        result["camera_robustness"] = dict(workload="c1_20k_4views_256", steps=300,
+                                           seconds=round(time.time() - t0, 1),
+                                           rows=[{k: (round(v, 6) if isinstance(v, float) else v)
+                                                  for k, v in r.items()} for r in rows])
     if not args.no_c5 and args.config == 3:
         log("[bench] training-step scale: 5M surfels, 50 views of 2048^2")
         bufs = graph = plan = None
@@ -484,7 +499,7 @@ def main():
         c5 = training_scale(args, tile=8, batch=64)
         result["training_step_c5"] = {k: c5[k] for k in ("value", "unit", "ms_per_step", "steps_per_s",
                                                          "steps", "peak_hbm_GB", "config", "pairs",
-                                                         "surrogate", "kernels")}
+                                                         "surrogate", "kernels", "loss_l1_last")}
     print(json.dumps(result), flush=True)
 
 

@@ -57,9 +57,76 @@ __device__ __forceinline__ double zbar_at(const float *D, const float *T, int64_
     return (double)D[g] / (1.0 - (double)T[g]);
 }
 
-// One thread per pixel of view blockIdx.y: depth normal, loss term, d_normal (added),
-// the z-adjoint seeds s = Minv[:, 2] . dL/dgrad p stored per pixel, and per block the
-// sums of the loss terms and of dL/dMinv (10 doubles).
+// Pixels of view blockIdx.y, kGeomPx per thread at a stride of the block size: depth
+// normal, loss term, d_normal (added), the z-adjoint seeds s = Minv[:, 2] . dL/dgrad p
+// stored per pixel, and per block the sums of the loss terms and of dL/dMinv (10 doubles),
+// reduced once per thread after its pixels.
+constexpr int kGeomPx = 8;
+
+__device__ __forceinline__ void normal_loss_pixel(
+    const ViewDesc &vd, int64_t local, const GeomCam &c, const float *__restrict__ D,
+    const float *__restrict__ T, const float *__restrict__ Nr, double wv, double tau,
+    float *__restrict__ Nd_out, float *__restrict__ d_normal, float2 *__restrict__ seeds,
+    double (&acc)[10])
+{
+    const int64_t P = (int64_t)vd.W * vd.H;
+    const int i = (int)(local % vd.W), j = (int)(local / vd.W);
+    const int64_t g = vd.pix_off + local;
+    const int64_t b3 = 3 * vd.pix_off + local;
+    bool valid = i > 0 && j > 0 && i < vd.W - 1 && j < vd.H - 1;
+    valid = valid && covered(T, g, tau) && covered(T, g - 1, tau) && covered(T, g + 1, tau) &&
+            covered(T, g - vd.W, tau) && covered(T, g + vd.W, tau);
+    float2 s = make_float2(0.f, 0.f);
+    float nd[3] = {0.f, 0.f, 0.f};
+    if (valid) {
+        const double *Mi = c.Minv;
+        const double dzx = zbar_at(D, T, g + 1) - zbar_at(D, T, g - 1);
+        const double dzy = zbar_at(D, T, g + vd.W) - zbar_at(D, T, g - vd.W);
+        double gx[3], gy[3], n[3];
+        for (int r = 0; r < 3; ++r) {
+            gx[r] = 2.0 * Mi[3 * r] + dzx * Mi[3 * r + 2];
+            gy[r] = 2.0 * Mi[3 * r + 1] + dzy * Mi[3 * r + 2];
+        }
+        n[0] = gx[1] * gy[2] - gx[2] * gy[1];
+        n[1] = gx[2] * gy[0] - gx[0] * gy[2];
+        n[2] = gx[0] * gy[1] - gx[1] * gy[0];
+        const double inn = 1.0 / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        const double sgn = (n[0] * c.d[0] + n[1] * c.d[1] + n[2] * c.d[2] > 0.0) ? -1.0 : 1.0;
+        double N[3], R[3];
+        for (int r = 0; r < 3; ++r) {
+            N[r] = sgn * n[r] * inn;
+            R[r] = (double)Nr[b3 + r * P];
+        }
+        acc[9] += 1.0 - (R[0] * N[0] + R[1] * N[1] + R[2] * N[2]);
+        for (int r = 0; r < 3; ++r) {
+            d_normal[b3 + r * P] += (float)(-wv * N[r]);
+            nd[r] = (float)N[r];
+        }
+        // dL/dN = -wv N_r -> dL/dn = sgn (gN - N (N . gN)) / |n|
+        double gN[3], gn[3];
+        for (int r = 0; r < 3; ++r) gN[r] = -wv * R[r];
+        const double pr = N[0] * gN[0] + N[1] * gN[1] + N[2] * gN[2];
+        for (int r = 0; r < 3; ++r) gn[r] = sgn * (gN[r] - N[r] * pr) * inn;
+        // n = gx x gy: dL/dgx = gy x gn, dL/dgy = gn x gx
+        const double ggx[3] = {gy[1] * gn[2] - gy[2] * gn[1], gy[2] * gn[0] - gy[0] * gn[2],
+                               gy[0] * gn[1] - gy[1] * gn[0]};
+        const double ggy[3] = {gn[1] * gx[2] - gn[2] * gx[1], gn[2] * gx[0] - gn[0] * gx[2],
+                               gn[0] * gx[1] - gn[1] * gx[0]};
+        s.x = (float)(Mi[2] * ggx[0] + Mi[5] * ggx[1] + Mi[8] * ggx[2]);
+        s.y = (float)(Mi[2] * ggy[0] + Mi[5] * ggy[1] + Mi[8] * ggy[2]);
+        // dL/dMinv = ggx (2, 0, dzx)^T + ggy (0, 2, dzy)^T
+        for (int r = 0; r < 3; ++r) {
+            acc[3 * r] += 2.0 * ggx[r];
+            acc[3 * r + 1] += 2.0 * ggy[r];
+            acc[3 * r + 2] += dzx * ggx[r] + dzy * ggy[r];
+        }
+    }
+    seeds[g] = s;
+    if (Nd_out) {
+        for (int r = 0; r < 3; ++r) Nd_out[b3 + r * P] = nd[r];
+    }
+}
+
 __global__ __launch_bounds__(kGeomThreads) void k_normal_loss(
     const ViewDesc *__restrict__ views, const GeomCam *__restrict__ cams,
     const float *__restrict__ D, const float *__restrict__ T, const float *__restrict__ Nr,
@@ -70,68 +137,15 @@ __global__ __launch_bounds__(kGeomThreads) void k_normal_loss(
     const int v = blockIdx.y;
     const ViewDesc vd = views[v];
     const int64_t P = (int64_t)vd.W * vd.H;
-    const int64_t local = (int64_t)blockIdx.x * kGeomThreads + threadIdx.x;
+    const GeomCam c = cams[v];
+    const double wv = weight / (double)P;
     double acc[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.0;
-    if (local < P) {
-        const int i = (int)(local % vd.W), j = (int)(local / vd.W);
-        const int64_t g = vd.pix_off + local;
-        const int64_t b3 = 3 * vd.pix_off + local;
-        bool valid = i > 0 && j > 0 && i < vd.W - 1 && j < vd.H - 1;
-        valid = valid && covered(T, g, tau) && covered(T, g - 1, tau) && covered(T, g + 1, tau) &&
-                covered(T, g - vd.W, tau) && covered(T, g + vd.W, tau);
-        float2 s = make_float2(0.f, 0.f);
-        float nd[3] = {0.f, 0.f, 0.f};
-        if (valid) {
-            const GeomCam c = cams[v];
-            const double *Mi = c.Minv;
-            const double dzx = zbar_at(D, T, g + 1) - zbar_at(D, T, g - 1);
-            const double dzy = zbar_at(D, T, g + vd.W) - zbar_at(D, T, g - vd.W);
-            double gx[3], gy[3], n[3];
-            for (int r = 0; r < 3; ++r) {
-                gx[r] = 2.0 * Mi[3 * r] + dzx * Mi[3 * r + 2];
-                gy[r] = 2.0 * Mi[3 * r + 1] + dzy * Mi[3 * r + 2];
-            }
-            n[0] = gx[1] * gy[2] - gx[2] * gy[1];
-            n[1] = gx[2] * gy[0] - gx[0] * gy[2];
-            n[2] = gx[0] * gy[1] - gx[1] * gy[0];
-            const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-            const double sgn = (n[0] * c.d[0] + n[1] * c.d[1] + n[2] * c.d[2] > 0.0) ? -1.0 : 1.0;
-            double N[3], R[3];
-            for (int r = 0; r < 3; ++r) {
-                N[r] = sgn * n[r] / nn;
-                R[r] = (double)Nr[b3 + r * P];
-            }
-            const double wv = weight / (double)P;
-            acc[9] = 1.0 - (R[0] * N[0] + R[1] * N[1] + R[2] * N[2]);
-            for (int r = 0; r < 3; ++r) {
-                d_normal[b3 + r * P] += (float)(-wv * N[r]);
-                nd[r] = (float)N[r];
-            }
-            // dL/dN = -wv N_r -> dL/dn = sgn (gN - N (N . gN)) / |n|
-            double gN[3], gn[3];
-            for (int r = 0; r < 3; ++r) gN[r] = -wv * R[r];
-            const double pr = N[0] * gN[0] + N[1] * gN[1] + N[2] * gN[2];
-            for (int r = 0; r < 3; ++r) gn[r] = sgn * (gN[r] - N[r] * pr) / nn;
-            // n = gx x gy: dL/dgx = gy x gn, dL/dgy = gn x gx
-            const double ggx[3] = {gy[1] * gn[2] - gy[2] * gn[1], gy[2] * gn[0] - gy[0] * gn[2],
-                                   gy[0] * gn[1] - gy[1] * gn[0]};
-            const double ggy[3] = {gn[1] * gx[2] - gn[2] * gx[1], gn[2] * gx[0] - gn[0] * gx[2],
-                                   gn[0] * gx[1] - gn[1] * gx[0]};
-            s.x = (float)(Mi[2] * ggx[0] + Mi[5] * ggx[1] + Mi[8] * ggx[2]);
-            s.y = (float)(Mi[2] * ggy[0] + Mi[5] * ggy[1] + Mi[8] * ggy[2]);
-            // dL/dMinv = ggx (2, 0, dzx)^T + ggy (0, 2, dzy)^T
-            for (int r = 0; r < 3; ++r) {
-                acc[3 * r] = 2.0 * ggx[r];
-                acc[3 * r + 1] = 2.0 * ggy[r];
-                acc[3 * r + 2] = dzx * ggx[r] + dzy * ggy[r];
-            }
-        }
-        seeds[g] = s;
-        if (Nd_out) {
-            for (int r = 0; r < 3; ++r) Nd_out[b3 + r * P] = nd[r];
-        }
+    const int64_t l0 = (int64_t)blockIdx.x * (kGeomThreads * kGeomPx) + threadIdx.x;
+    for (int r = 0; r < kGeomPx; ++r) {
+        const int64_t local = l0 + (int64_t)r * kGeomThreads;
+        if (local < P) normal_loss_pixel(vd, local, c, D, T, Nr, wv, tau, Nd_out, d_normal, seeds, acc);
     }
     // block sums: wave shuffles, then the waves' sums through LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -205,7 +219,7 @@ __global__ void k_normal_loss_reduce(const ViewDesc *__restrict__ views,
 
 int normal_loss_blocks(int64_t max_view_pixels)
 {
-    return (int)((max_view_pixels + kGeomThreads - 1) / kGeomThreads);
+    return (int)((max_view_pixels + kGeomThreads * kGeomPx - 1) / (kGeomThreads * kGeomPx));
 }
 
 hipError_t launch_normal_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pixels,
@@ -222,7 +236,8 @@ hipError_t launch_normal_loss(const ViewDesc *views, int32_t nv, int64_t max_vie
         hipLaunchKernelGGL(k_normal_loss, dim3((unsigned)bpv, (unsigned)nv), dim3(kGeomThreads), 0, st,
                            views, cams, D, T, Nr, (double)weight, (double)tau, Nd_out, d_normal,
                            seeds, partials, bpv);
-        hipLaunchKernelGGL(k_normal_loss_depth, dim3((unsigned)bpv, (unsigned)nv), dim3(kGeomThreads),
+        const int dbl = (int)((max_view_pixels + kGeomThreads - 1) / kGeomThreads);
+        hipLaunchKernelGGL(k_normal_loss_depth, dim3((unsigned)dbl, (unsigned)nv), dim3(kGeomThreads),
                            0, st, views, T, (double)tau, seeds, d_depth);
     }
     hipLaunchKernelGGL(k_normal_loss_reduce, dim3((unsigned)((nv + 63) / 64)), dim3(64), 0, st, views,

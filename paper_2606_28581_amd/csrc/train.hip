@@ -178,31 +178,38 @@ __global__ void k_adam_views(int32_t nv, float *__restrict__ dF, float *__restri
 }
 
 // L1 image loss: per view weight / (3 P) sum |I - I*|; d_image = weight sign(I - I*) / (3 P).
-// Grid (blocks per view, views); partials: per (view, block) one double.
+// Grid (blocks per view, views); each thread takes kL1PerThread elements at a stride of the
+// block size (coalesced), sums |d| in FP32, and the block's sum goes to one FP64 partial.
+constexpr int kL1PerThread = 8;
+
 __global__ __launch_bounds__(kTrainThreads) void k_l1_loss(
     const ViewDesc *__restrict__ views, const float *__restrict__ img,
     const float *__restrict__ tgt, float weight, float *__restrict__ d_img,
     double *__restrict__ partials, int blocks_per_view)
 {
-    __shared__ double red[kTrainThreads / 64];
+    __shared__ float red[kTrainThreads / 64];
     const int v = blockIdx.y;
     const ViewDesc vd = views[v];
     const int64_t n = 3 * (int64_t)vd.W * vd.H;
-    const int64_t k = (int64_t)blockIdx.x * kTrainThreads + threadIdx.x;
-    double s = 0.0;
-    if (k < n) {
-        const int64_t at = 3 * vd.pix_off + k;
-        const float d = img[at] - tgt[at];
-        s = fabs((double)d);
-        const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        d_img[at] = (float)((double)weight * sg / (double)n);
+    const float step = (float)((double)weight / (double)n);
+    const int64_t k0 = (int64_t)blockIdx.x * (kTrainThreads * kL1PerThread) + threadIdx.x;
+    const int64_t base = 3 * vd.pix_off;
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < kL1PerThread; ++r) {
+        const int64_t k = k0 + (int64_t)r * kTrainThreads;
+        if (k < n) {
+            const float d = img[base + k] - tgt[base + k];
+            s += fabsf(d);
+            d_img[base + k] = d > 0.f ? step : (d < 0.f ? -step : 0.f);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < kTrainThreads / 64; ++w) t += red[w];
+        for (int w = 0; w < kTrainThreads / 64; ++w) t += (double)red[w];
         partials[(size_t)v * blocks_per_view + blockIdx.x] = t;
     }
 }
@@ -270,7 +277,10 @@ hipError_t launch_adam_views(int32_t nv, float *dF, float *m_dF, float *v_dF, co
     return hipGetLastError();
 }
 
-int l1_blocks(int64_t max_view_pixels) { return (int)blocks_for(3 * max_view_pixels); }
+int l1_blocks(int64_t max_view_pixels)
+{
+    return (int)((3 * max_view_pixels + kTrainThreads * kL1PerThread - 1) / (kTrainThreads * kL1PerThread));
+}
 
 hipError_t launch_l1_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pixels,
                           const float *img, const float *tgt, float weight, float *d_img,

@@ -152,9 +152,12 @@ def init_params(seed):
     return w
 
 
-def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, log=print):
+def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, log=print,
+             bands=(0.0, 0.02, 0.05, 0.1, 0.2, 0.3)):
     """Held-out suns: agreement of the surrogate (with fallback) and of the bare network
-    with the plain pass, fallback fraction, and ms per view of both passes."""
+    with the plain pass, fallback fraction, and ms per view of both passes; `curve` gives
+    agreement, fallback fraction and ms per view of the surrogate pass for each
+    fallback band."""
     dev = lab.surf.mean.device
     if train_suns is None:
         train_suns = draw_suns(cfg.train_suns, cfg.sun_elev_deg, cfg.train_seed)
@@ -162,6 +165,7 @@ def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, 
     sun_t = torch.as_tensor(suns, device=dev)
     agree = agree_net = fallback = total = lit = 0
     t_plain = t_sur = 0.0
+    cur = {b: dict(agree=0, fallback=0, ms=0.0) for b in bands}
     ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     plan = lab.plan
     for s0 in range(0, cfg.eval_suns, lab.chunk):
@@ -181,8 +185,16 @@ def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, 
         torch.cuda.synchronize()
         t_sur += ev_a.elapsed_time(ev_b)
         fallback += plan.stats()["fallback"] * nv // lab.chunk
+        agree_main = ((vis[:nv] >= 0.5) == (ref[:nv] >= 0.5)).sum().item()
+        for b in bands:
+            sg.shadow_surrogate(plan, net, w, lab.surf, v, band=b)      # warm
+            ev_a.record(); vb = sg.shadow_surrogate(plan, net, w, lab.surf, v, band=b); ev_b.record()
+            torch.cuda.synchronize()
+            cur[b]["ms"] += ev_a.elapsed_time(ev_b)
+            cur[b]["fallback"] += plan.stats()["fallback"] * nv // lab.chunk
+            cur[b]["agree"] += ((vb[:nv] >= 0.5) == (ref[:nv] >= 0.5)).sum().item()
         p = net.forward(w, lab.surf.mean, s.contiguous(), all_pairs=True, prob=True).view(lab.chunk, -1)
-        agree += ((vis[:nv] >= 0.5) == (ref[:nv] >= 0.5)).sum().item()
+        agree += agree_main
         agree_net += ((p[:nv] >= 0.5) == (ref[:nv] >= 0.5)).sum().item()
         lit += (ref[:nv] >= 0.5).sum().item()
         total += ref[:nv].numel()
@@ -191,6 +203,9 @@ def evaluate(lab: ShadowLab, net: sg.Mlp, w, cfg: TrainConfig, train_suns=None, 
                agreement=round(agree / total, 5), agreement_network_only=round(agree_net / total, 5),
                fallback_fraction=round(fallback / total, 5), lit_fraction=round(lit / total, 5),
                plain_ms_per_view=round(t_plain / nviews, 4),
-               surrogate_ms_per_view=round(t_sur / nviews, 4))
+               surrogate_ms_per_view=round(t_sur / nviews, 4),
+               curve=[dict(band=b, agreement=round(c["agree"] / total, 5),
+                           fallback_fraction=round(c["fallback"] / total, 5),
+                           ms_per_view=round(c["ms"] / nviews, 4)) for b, c in cur.items()])
     log(f"[surrogate] eval: {res}")
     return res

@@ -116,13 +116,17 @@ class Trainer:
         self.out = None
         self.loss_l1 = torch.empty(nv, dtype=torch.float32, device=dev)
         self.step_count = 0
+        # read the plan's overflow flag after every forward (a host synchronisation) and
+        # grow the workspace when needed; off for timing loops that check once at the end
+        self.check = True
 
     def step(self):
         """One training step; returns (per-view L1 loss, per-view normal loss) tensors (the
         L1 buffer is the trainer's own and is overwritten by the next step)."""
         self.step_count += 1
         vis = self.vis() if callable(self.vis) else self.vis
-        self.out = self.plan.forward(self.surf, self.views, vis, out=self.out, depth_scale=self.ds)
+        self.out = self.plan.forward(self.surf, self.views, vis, out=self.out, depth_scale=self.ds,
+                                     check=self.check)
         image_loss_l1(self.plan, self.out["image"], self.targets, self.w.l1, self.d_image,
                       self.loss_l1)
         self.d_depth.zero_()
