@@ -288,6 +288,28 @@ ss_status ss_adam_views(int32_t nv, float *dF, float *m_dF, float *v_dF, const f
 ss_status ss_image_loss_l1(ss_plan *plan, const float *image, const float *target, float weight,
                            float *loss, float *d_image, ss_stream stream);
 
+/* ------------------------------------------------- geometry-aware initialisation
+ * Initial surfels on a DSM (Sec. 3.4 "Area-Weighted Sampling", "Splat Orientation").
+ * z: device [ny, nx] FP32 node heights at (x0 + i gsd, y0 + j gsd); cell (j, i) spans
+ * nodes j..j+1, i..i+1.  Each cell's tangents are (g, 0, dzx) and (0, g, dzy) (dzx, dzy
+ * the means of its two edge differences), its area a = |dx x dy| and its normal
+ * (-dzx, -dzy, g) / |.|; its sampling weight is the integer floor(65536 a / g^2 + 1/2).
+ * Sample k (0 <= k < n) draws Philox4x32-10 with key (seed & 0xffffffff, seed >> 32) at
+ * counters (k, 0, 0, 0) = r0..r3 and (k, 1, 0, 0) = r4..r7: the cell is the first whose
+ * cumulative weight (row-major) exceeds (r1 2^32 + r0) mod W (W the total weight); the
+ * centre is at fractional position (r2, r3) / 2^32 in the cell with bilinear height;
+ * t_u = normalise(r - (r . n) n) for r = (r4, r5, r6) / 2^31 - 1 (the x axis if that is
+ * shorter than 1e-6), t_v = n x t_u; s_u = s_v = sqrt(W g^2 / 65536 / n) (the spacing of
+ * n samples over the surface area); opacity and albedo take the given values.
+ * Outputs: the ss_surfels arrays of the n surfels, and cell [n] (or NULL) the chosen
+ * cell index.  Workspace: device memory of ss_dsm_init_workspace_size bytes, 256-byte
+ * aligned. */
+ss_status ss_dsm_init_workspace_size(int32_t nx, int32_t ny, size_t *bytes);
+ss_status ss_dsm_init(int32_t nx, int32_t ny, const float *z, float x0, float y0, float gsd,
+                      int64_t n, uint64_t seed, float opacity, float albedo, void *workspace,
+                      size_t bytes, float *mean, float *t_u, float *t_v, float *scale,
+                      float *opacity_out, float *albedo_out, int64_t *cell, ss_stream stream);
+
 /* -------------------------------------------------------------- shadow pass
  * Geometric sun-view shadow map (Sec. 3.3 Eq. sun_camera_Bxy, Supp. A; Sec. 3.1 soft
  * shadow test).  Per view: sun camera B_sun = lam * B'_xy (I - [0 0 s]) with

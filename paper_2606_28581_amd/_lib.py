@@ -95,6 +95,10 @@ _SIGS = {
     "ss_normal_loss": (C.c_int32, [_P, C.POINTER(Views), _P, _P, _P, C.c_float, C.c_float, _P,
                                    _P, _P, _P, _P, _P]),
     "ss_surfel_activate": (C.c_int32, [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ss_dsm_init_workspace_size": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "ss_dsm_init": (C.c_int32, [C.c_int32, C.c_int32, _P, C.c_float, C.c_float, C.c_float, C.c_int64,
+                                C.c_uint64, C.c_float, C.c_float, _P, C.c_size_t, _P, _P, _P, _P, _P,
+                                _P, _P, _P]),
     "ss_surfel_raw": (C.c_int32, [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ss_adam_surfels": (C.c_int32, [C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                     C.POINTER(AdamConfig), C.c_int32, _P, _P, _P, _P, _P, _P, _P]),

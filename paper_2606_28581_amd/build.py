@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsatsplat.so")
-SOURCES = ["sort.hip", "raster.hip", "shadow.hip", "mlp.hip", "geom.hip", "train.hip", "api.hip"]
+SOURCES = ["sort.hip", "raster.hip", "shadow.hip", "mlp.hip", "geom.hip", "train.hip", "init.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

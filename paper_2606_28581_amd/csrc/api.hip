@@ -1423,6 +1423,34 @@ ss_status ss_image_loss_l1(ss_plan *p, const float *image, const float *target, 
     return SS_OK;
 }
 
+ss_status ss_dsm_init_workspace_size(int32_t nx, int32_t ny, size_t *bytes)
+{
+    if (!bytes || nx < 2 || ny < 2) return fail(SS_ERR_INVALID_ARG, "the DSM needs at least 2 x 2 nodes");
+    *bytes = dsm_init_workspace_bytes(nx, ny);
+    return SS_OK;
+}
+
+ss_status ss_dsm_init(int32_t nx, int32_t ny, const float *z, float x0, float y0, float gsd,
+                      int64_t n, uint64_t seed, float opacity, float albedo, void *workspace,
+                      size_t bytes, float *mean, float *t_u, float *t_v, float *scale,
+                      float *opacity_out, float *albedo_out, int64_t *cell, ss_stream stream)
+{
+    if (nx < 2 || ny < 2 || !z) return fail(SS_ERR_INVALID_ARG, "the DSM needs at least 2 x 2 nodes");
+    if ((int64_t)(nx - 1) * (int64_t)(ny - 1) > (int64_t(1) << 36))
+        return fail(SS_ERR_UNSUPPORTED, "DSM too large");
+    if (!(gsd > 0.f) || !std::isfinite(gsd) || !std::isfinite(x0) || !std::isfinite(y0))
+        return fail(SS_ERR_INVALID_ARG, "gsd must be positive, the origin finite");
+    if (n < 0 || n > (int64_t(1) << 32)) return fail(SS_ERR_INVALID_ARG, "n must be in [0, 2^32]");
+    if (!workspace || bytes < dsm_init_workspace_bytes(nx, ny) || ((uintptr_t)workspace & 255))
+        return fail(SS_ERR_CAPACITY, "workspace missing, unaligned or smaller than ss_dsm_init_workspace_size");
+    if (n > 0 && (!mean || !t_u || !t_v || !scale || !opacity_out || !albedo_out))
+        return fail(SS_ERR_INVALID_ARG, "NULL output");
+    SS_HIP(launch_dsm_init(nx, ny, z, (double)x0, (double)y0, (double)gsd, n, seed, opacity, albedo,
+                           workspace, mean, t_u, t_v, scale, opacity_out, albedo_out, cell,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return SS_OK;
+}
+
 static const char *kStageNames[SS_NUM_STAGES] = {
     "depth_sort", "project", "bin", "raster_fwd", "raster_bwd", "project_bwd", "reduce",
     "sun_camera", "sun_project", "sun_bin", "sun_raster", "shadow_query", "mlp_forward",

@@ -260,6 +260,13 @@ hipError_t launch_l1_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pi
                           const float *img, const float *tgt, float weight, float *d_img,
                           double *partials, float *loss, hipStream_t st);
 
+// init.hip: geometry-aware initialisation on a DSM (area-weighted sampling, frames).
+size_t dsm_init_workspace_bytes(int nx, int ny);
+hipError_t launch_dsm_init(int nx, int ny, const float *z, double x0, double y0, double g, int64_t n,
+                           uint64_t seed, float opacity, float albedo, void *ws, float *mean,
+                           float *tu, float *tv, float *scale, float *opac, float *alb,
+                           int64_t *cell, hipStream_t st);
+
 // shadow.hip
 int bounds_blocks(int64_t n);
 hipError_t launch_sun_cameras(const float *mean, int64_t n, int32_t nv, const float *Fxy,
