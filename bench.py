@@ -316,6 +316,29 @@ def training_scale(args, tile=None, batch=None):
     }
 
 
+def dsm_init_timing(reps=5):
+    """Geometry-aware initialisation of the 5M surfels of the 2 x 2 km city from its DSM
+    (Sec. 3.4): weights, prefix sum and sampling, HIP events around the whole call."""
+    import numpy as np
+    import torch
+    import synth
+    from synth.scene import _streams, make_dsm
+    from paper_2606_28581_amd import init as gi
+    spec = synth.config(5)
+    coords, z = make_dsm(spec, _streams(spec.seed)["scene"])
+    zt = torch.as_tensor(z.astype(np.float32), device="cuda")
+    x0 = float(coords[0])
+    gi.dsm_init(zt, x0, x0, spec.gsd, spec.n_surfels, seed=1)      # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        gi.dsm_init(zt, x0, x0, spec.gsd, spec.n_surfels, seed=1 + r)
+    e1.record()
+    e1.synchronize()
+    return dict(workload="c5 DSM 4001^2 nodes -> 5M surfels", ms=round(e0.elapsed_time(e1) / reps, 3),
+                cells=int((z.shape[0] - 1) * (z.shape[1] - 1)), surfels=spec.n_surfels)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -496,6 +519,8 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         torch.cuda.reset_peak_memory_stats()
+        result["dsm_init"] = dsm_init_timing()
+        torch.cuda.empty_cache()
         c5 = training_scale(args, tile=8, batch=64)
         result["training_step_c5"] = {k: c5[k] for k in ("value", "unit", "ms_per_step", "steps_per_s",
                                                          "steps", "peak_hbm_GB", "config", "pairs",
