@@ -15,7 +15,8 @@ Recipe (each step follows the paper's description of its data and initialisation
     bilinear surface.
   * Frames from the local DSM normal tilted by N(0, 5 deg), tangent axes by Gram-Schmidt
     of a random vector (Sec. 3.4, "Splat Orientation").
-  * Scales log-uniform in [0.2, 2] m, opacity sigmoid(N(0,1)), albedo U[0,1]^3.
+  * Scales log-uniform in [0.2, 2] m, opacity sigmoid(N(0,1)), albedo U[0,1]^3 (the
+    shadow ground-truth scenes use small opaque surfels instead: `shadow_city`).
   * Affine cameras from off-nadir / azimuth with a small random affine distortion of the
     image axes, mapping world metres to pixels (Sec. 3.1, "Affine camera model").
   * Camera deltas, colour gain/bias, ambient light and sun angles as the configurations
@@ -53,6 +54,9 @@ class SceneSpec:
     gsd: float = 0.5                # DSM grid spacing, metres
     fill: float = 0.95              # fraction of the image the scene box fills
     seed: int = 0
+    scale_range: Tuple[float, float] = (0.2, 2.0)  # surfel scales, log-uniform, metres
+    opacity: Optional[float] = None  # fixed opacity (None: sigmoid(N(0, 1)))
+    tilt_deg: float = 5.0           # std of the normal's tilt from the DSM normal
 
 
 def _streams(seed: int):
@@ -153,13 +157,16 @@ def sample_surfels(spec: SceneSpec, coords, z, rng):
     # tilt by N(0, 5 deg) about a random tangent axis
     r = rng.normal(size=(n, 3))
     axis = _unit(r - np.sum(r * normal, axis=1, keepdims=True) * normal)
-    normal = _unit(_rotate(normal, axis, np.deg2rad(rng.normal(0.0, 5.0, size=n))))
+    normal = _unit(_rotate(normal, axis, np.deg2rad(rng.normal(0.0, spec.tilt_deg, size=n))))
     # Gram-Schmidt frame
     r = rng.normal(size=(n, 3))
     t_u = _unit(r - np.sum(r * normal, axis=1, keepdims=True) * normal)
     t_v = np.cross(normal, t_u)
-    scale = np.exp(rng.uniform(np.log(0.2), np.log(2.0), size=(n, 2)))
+    lo, hi = spec.scale_range
+    scale = np.exp(rng.uniform(np.log(lo), np.log(hi), size=(n, 2)))
     opacity = 1.0 / (1.0 + np.exp(-rng.normal(size=n)))
+    if spec.opacity is not None:
+        opacity = np.full(n, spec.opacity)
     albedo = rng.uniform(0.0, 1.0, size=(n, 3))
     f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return dict(mean=f32(mean), t_u=f32(t_u), t_v=f32(t_v), scale=f32(scale),
@@ -272,3 +279,12 @@ def tiny(n_surfels=48, views=((40, 33),), extent=24.0, n_boxes=2, seed=7, colour
     return SceneSpec(f"tiny_{n_surfels}", extent, n_boxes, box_side, box_height, 0.0,
                      n_surfels, list(views), dF_rel=dF_rel, colour=colour, suns=suns,
                      seed=seed, gsd=gsd)
+
+
+def shadow_city(n_surfels=30_000, extent=48.0, n_boxes=6, views=3, seed=5):
+    """A city whose surfels follow the DSM closely (0.3 m, opacity 0.95, no tilt), so that
+    the DSM heightfield is the ground truth of its shadows; one 64^2 nadir-ish view per
+    sun (the views only carry the suns)."""
+    return SceneSpec(f"shadow_city_{n_surfels}", extent, n_boxes, (6.0, 14.0), (3.0, 12.0), 0.0,
+                     n_surfels, [(64, 64)] * views, suns=True, seed=seed,
+                     scale_range=(0.3, 0.3), opacity=0.95, tilt_deg=0.0)

@@ -71,3 +71,24 @@ def test_sun_records_centre_box_and_unstored_fields():
         np.testing.assert_array_equal(lo[live, 1], pix[live, 2])
         np.testing.assert_array_equal(hi[live, 1], pix[live, 3])
         assert not rec[v][:, 16:].any()
+
+
+def test_plain_pass_agrees_with_heightfield_ground_truth():
+    """On a city whose surfels follow the DSM closely, every surfel of flat ground or roof
+    whose sun visibility is clear of the edge band gets the heightfield ray march's
+    decision from the GPU's plain pass (tile 8, 256^2 sun maps)."""
+    from shadow_truth import confident_flat
+    sc = synth.make_scene(synth.shadow_city(n_boxes=8, seed=5))
+    plan, surf, views = make_plan(sc, ts=8, S=256, with_sun=True)
+    vis = to_np(plan.shadow(surf, views))
+    n = sc["surfels"]["mean"].shape[0]
+    sel = np.arange(n)
+    dark = 0
+    for v in range(len(sc["width"])):
+        m, conf = confident_flat(sc, sel, v)
+        agree = (vis[v] >= 0.5) == (m < 0)
+        dark += int((conf & (m > 0)).sum())
+        print(f"[shadow-gt] view {v}: {int(conf.sum())} confident surfels, agreement "
+              f"{agree[conf].mean():.5f}", flush=True)
+        assert agree[conf].all(), (v, np.flatnonzero(conf & ~agree)[:10])
+    assert dark > 1500
