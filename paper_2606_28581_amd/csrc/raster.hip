@@ -929,11 +929,19 @@ __device__ __forceinline__ DistPixel pixel_distortion_state(bool inside, int64_t
 // Gradients of one (record, pixel) pair in the back-to-front walk.  Updates the pixel's
 // transmittance Tr and suffix gS when the pair contributes, returns the 16 record
 // gradient values in gr (zero when it does not).
+//
+// The branch of the pair (ub: the surfel's own Gaussian, else the low-pass disk) enters
+// once, by zeroing u (and the depth gradient that flows into u) on the low-pass branch:
+// z = z0 - k . u then equals the centre depth z0, and every u-branch term (the k and Q
+// gradients, the centre gradient through Q) vanishes by multiplication; the low-pass
+// term of the centre gradient is zeroed on the u branch the same way.  With
+// rho2 = d alpha / d rho * 2 = -oG dal (unclamped), the centre gradient is
+//   dL/dc = -(Q^T dL/du + delta rho2 / sigma^2 [low-pass branch]).
 template <bool DIST>
 __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, float4 r2,
                                                float4 r3, float4 r4, float4 r5,
                                                const PixelAdjoint &pa, const DistPixel &dp,
-                                               bool has_vis, float two_is2, float alpha_max,
+                                               bool has_vis, float inv_s2, float alpha_max,
                                                float ds, float &Tr, float &gS, float (&gr)[16])
 {
     // gradient arithmetic with explicit fused multiply-adds (the discrete decisions -
@@ -941,7 +949,8 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
     const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
     const float Tb = Tr * rom;
     const float w = contrib ? e.alpha * Tb : 0.f;
-    const float z = e.ub ? __fmaf_rn(-r3.z, e.u0, __fmaf_rn(-r3.w, e.u1, r3.y)) : r3.y;
+    const float u0 = e.ub ? e.u0 : 0.f, u1 = e.ub ? e.u1 : 0.f;
+    const float z = __fmaf_rn(-r3.z, u0, __fmaf_rn(-r3.w, u1, r3.y));
     float gf = fmaf(pa.gA0, r4.x, fmaf(pa.gA1, r4.y, fmaf(pa.gA2, r4.z, fmaf(pa.gD, z,
                fmaf(pa.gN0, r5.x, fmaf(pa.gN1, r5.y, pa.gN2 * r5.z))))));
     if (has_vis) gf = fmaf(pa.gV, r4.w, gf);
@@ -956,27 +965,24 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
     gS = fmaf(w, gf, gS);
     Tr = contrib ? Tb : Tr;
     const float dz = w * gDe;
+    const float dzu = e.ub ? dz : 0.f;
     gr[G_AR] = w * pa.gA0; gr[G_AG] = w * pa.gA1; gr[G_AB] = w * pa.gA2;
     gr[G_NX] = w * pa.gN0; gr[G_NY] = w * pa.gN1; gr[G_NZ] = w * pa.gN2;
     gr[G_Z0] = dz;
-    const bool unclamped = e.oG < alpha_max;
-    gr[G_O] = unclamped ? e.G * dal : 0.f;
-    const float dG = unclamped ? r3.x * dal : 0.f;
-    const float drho = -0.5f * e.G * dG;
-    const float drho2 = drho + drho;
-    const float du0 = fmaf(e.u0, drho2, -r3.z * dz);
-    const float du1 = fmaf(e.u1, drho2, -r3.w * dz);
-    gr[G_KU] = e.ub ? -e.u0 * dz : 0.f;
-    gr[G_KV] = e.ub ? -e.u1 * dz : 0.f;
-    gr[G_Q00] = e.ub ? du0 * e.dx : 0.f;
-    gr[G_Q01] = e.ub ? du0 * e.dy : 0.f;
-    gr[G_Q10] = e.ub ? du1 * e.dx : 0.f;
-    gr[G_Q11] = e.ub ? du1 * e.dy : 0.f;
-    const float fdrho = two_is2 * drho;
-    const float ddx = e.ub ? fmaf(r2.x, du0, r2.z * du1) : e.dx * fdrho;
-    const float ddy = e.ub ? fmaf(r2.y, du0, r2.w * du1) : e.dy * fdrho;
-    gr[G_CX] = -ddx;
-    gr[G_CY] = -ddy;
+    const float gd = e.oG < alpha_max ? dal : 0.f;       // zero where alpha is clamped
+    gr[G_O] = e.G * gd;
+    const float rho2 = -(e.oG * gd);
+    const float du0 = fmaf(u0, rho2, -r3.z * dzu);
+    const float du1 = fmaf(u1, rho2, -r3.w * dzu);
+    gr[G_KU] = -u0 * dz;
+    gr[G_KV] = -u1 * dz;
+    gr[G_Q00] = du0 * e.dx;
+    gr[G_Q01] = du0 * e.dy;
+    gr[G_Q10] = du1 * e.dx;
+    gr[G_Q11] = du1 * e.dy;
+    const float nfd = e.ub ? 0.f : -(inv_s2 * rho2);
+    gr[G_CX] = fmaf(-r2.x, du0, fmaf(-r2.z, du1, e.dx * nfd));
+    gr[G_CY] = fmaf(-r2.y, du0, fmaf(-r2.w, du1, e.dy * nfd));
 }
 
 // --------------------------------------------------------------- raster backward
@@ -995,7 +1001,7 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
 // lane, so one instruction carries the sums of up to four records.
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
-template <int TS, bool HAS_VIS, bool DIST>
+template <int TS, bool HAS_VIS, bool DIST, bool CM>
 __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 5 : 4))) void k_raster_bwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
@@ -1060,7 +1066,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
     float gS = 0.f;
     const int batch = min(rc.batch, NT);
-    const float two_is2 = rc.two_inv_s2;
+    const float inv_s2 = rc.two_inv_s2 * 0.5f;
     const int blk_last = min(max_last, tile_len);   // a stale `last` cannot read past the list
     // the row walks records up to the largest `last` among its 16 pixels
     const int row_last = row_max(mylast);
@@ -1076,7 +1082,8 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     }
     // batches on the forward's grid ([k * batch, (k + 1) * batch) from the list start),
     // back to front; the first one is cut at the tile's largest `last`
-    const bool use_cm = TS == 8 && cmask != nullptr;
+    constexpr bool use_cm = CM;              // 8x8 tiles with the forward's contributor masks
+    static_assert(!CM || TS == 8, "contributor masks exist for 8x8 tiles only");
     const size_t wbase = (size_t)(start >> 6) + (size_t)tile;
     const int pidx = ((py - wy0) << 3) | (px - wx0);   // the forward's lane of this pixel
     const int nbat = (blk_last + batch - 1) / batch;
@@ -1098,7 +1105,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
         for (int c0 = ((nb - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
             const int cnt = min(64, nb - c0);
             uint64_t m = 0, own = 0;
-            if (use_cm) {
+            if constexpr (use_cm) {
                 // the row walks the records any of its 16 pixels composited in the forward;
                 // a lane takes part only where its own pixel did (its forward mask bit)
                 const int P0 = bb + c0, sh = P0 & 63;
@@ -1145,19 +1152,19 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 // the forward's own decision for this pair: its mask bit (8x8 tiles), else
                 // the same FP32 alpha test inside the pixel's FP64 box (the forward never
                 // evaluates a pair outside it)
-                bool fwd_took;
-                if (use_cm) {
-                    fwd_took = (own >> jl) & 1ull;
+                // (a set mask bit also implies the pair lies before the pixel's `last`)
+                bool contrib;
+                if constexpr (use_cm) {
+                    contrib = act && ((own >> jl) & 1ull);
                 } else {
                     const uint32_t bx = __float_as_uint(r0.x), by = __float_as_uint(r0.y);
                     const int xlo = (int)(int16_t)(bx & 0xFFFFu), xhi = (int)(int16_t)(bx >> 16);
                     const int ylo = (int)(int16_t)(by & 0xFFFFu), yhi = (int)(int16_t)(by >> 16);
-                    fwd_took = px >= xlo && px <= xhi && py >= ylo && py <= yhi &&
-                               e.alpha >= rc.alpha_min;
+                    contrib = act && bb + j < mylast && px >= xlo && px <= xhi && py >= ylo &&
+                              py <= yhi && e.alpha >= rc.alpha_min;
                 }
-                const bool contrib = act && bb + j < mylast && fwd_took;
                 float gr[16];
-                pair_gradients<DIST>(e, contrib, r2, r3, r4, r5, pa, dp, HAS_VIS, two_is2,
+                pair_gradients<DIST>(e, contrib, r2, r3, r4, r5, pa, dp, HAS_VIS, inv_s2,
                                      rc.alpha_max, da.ds, Tr, gS, gr);
                 const uint64_t cb = __ballot(contrib);
                 if (cb == 0) continue;
@@ -1171,6 +1178,28 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
 #undef SS_FETCH_BWD
 }
 
+template <int TS, bool HV, bool DIST>
+static void launch_bwd_d(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
+                         const ViewDesc *views, const uint32_t *ranges, const uint32_t *lists,
+                         const float *rec, int64_t n, const RasterConsts &rc,
+                         const float *colC, const float *colc, const float *amb,
+                         const float *A, const float *V, const float *T, const int32_t *last,
+                         const float *dI, const float *dD, const float *dN, float *recgrad,
+                         float *cp, const unsigned long long *cmask, const DistArgs &da)
+{
+    if constexpr (TS == 8) {
+        if (cmask) {
+            hipLaunchKernelGGL((k_raster_bwd<TS, HV, DIST, true>), grid, dim3(TS * TS), lds, st, nv,
+                               views, ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc,
+                               colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_raster_bwd<TS, HV, DIST, false>), grid, dim3(TS * TS), lds, st, nv, views,
+                       ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc, amb,
+                       A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+}
+
 template <int TS, bool HV>
 static void launch_bwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const ViewDesc *views, const uint32_t *ranges, const uint32_t *lists,
@@ -1182,13 +1211,11 @@ static void launch_bwd_t(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
 {
     const DistArgs da = dist ? *dist : DistArgs{0.f, nullptr, nullptr, nullptr, 0};
     if (dist)
-        hipLaunchKernelGGL((k_raster_bwd<TS, HV, true>), grid, dim3(TS * TS), lds, st, nv, views,
-                           ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
-                           amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+        launch_bwd_d<TS, HV, true>(grid, lds, st, nv, views, ranges, lists, rec, n, rc, colC, colc,
+                                   amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
     else
-        hipLaunchKernelGGL((k_raster_bwd<TS, HV, false>), grid, dim3(TS * TS), lds, st, nv, views,
-                           ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc,
-                           amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+        launch_bwd_d<TS, HV, false>(grid, lds, st, nv, views, ranges, lists, rec, n, rc, colC, colc,
+                                    amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
 }
 
 hipError_t launch_raster_bwd(int ts, bool has_vis, int32_t total_tiles, int32_t nv,
