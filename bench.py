@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--tile-order", type=int, default=0, choices=(0, 1),
+                    help="raster dispatch order: 0 static XCD chunks (default), 1 heavy tiles first per XCD")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="eager steps instead of a HIP graph")
     ap.add_argument("--no-autotune", action="store_true")
@@ -241,7 +243,8 @@ def training_scale(args, tile=None, batch=None):
     ctx = ss.Context(0)
     surf, views = ss.scene_to_device(scene, with_sun=True)
     N, V, P = surf.mean.shape[0], len(views.width), views.pixels
-    settings = ss.default_settings(tile_size=tile or args.tile, batch_depth=batch or args.batch)
+    settings = ss.default_settings(tile_size=tile or args.tile, batch_depth=batch or args.batch,
+                                   tile_order=args.tile_order)
     plan = ss.Plan(ctx, N, views.width, views.height, settings)
     K, Ks = plan.ensure_capacity(surf, views)
     log(f"[bench] pairs main {K}, sun {Ks}, pixels {P}, workspace {plan.workspace.numel() / 2**30:.1f} GiB")
@@ -372,7 +375,8 @@ def main():
     ctx = ss.Context(0)
     surf, views = ss.scene_to_device(scene, with_sun=True)
     has_sun = views.sun is not None
-    settings = ss.default_settings(tile_size=args.tile, batch_depth=args.batch)
+    settings = ss.default_settings(tile_size=args.tile, batch_depth=args.batch,
+                                   tile_order=args.tile_order)
     plan = ss.Plan(ctx, surf.mean.shape[0], views.width, views.height, settings)
     K, Ks = plan.ensure_capacity(surf, views)
     P = views.pixels

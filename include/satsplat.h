@@ -70,6 +70,10 @@ typedef struct ss_raster_settings {
     float    esm_c;         /* exponential-shadow-map sharpness, 1/m (2.0)              */
     float    esm_bias;      /* shadow depth bias, m (0.5)                               */
     int32_t  sun_map_size;  /* S: sun-view depth map is S x S (1024)                    */
+    int32_t  tile_order;    /* raster dispatch order: 0 = static (tiles dealt to the 8
+                               XCDs in chunks of neighbouring tiles; default); 1 = the
+                               same assignment with each XCD's tiles of at least twice
+                               the mean list length dispatched first                   */
 } ss_raster_settings;
 
 /* Surfels, structure of arrays, FP32 device memory (Sec. 3.1 2DGS parameterisation).

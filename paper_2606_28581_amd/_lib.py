@@ -24,7 +24,8 @@ class RasterSettings(C.Structure):
                 ("batch_depth", C.c_int32), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("lowpass_sigma", C.c_float),
                 ("lowpass_mode", C.c_int32), ("det_rel_eps", C.c_float), ("esm_c", C.c_float),
-                ("esm_bias", C.c_float), ("sun_map_size", C.c_int32)]
+                ("esm_bias", C.c_float), ("sun_map_size", C.c_int32),
+                ("tile_order", C.c_int32)]
 
 
 class Surfels(C.Structure):

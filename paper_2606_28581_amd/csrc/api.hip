@@ -57,6 +57,7 @@ struct Layout {
     size_t pk_a, pv_a, pk_b, pv_b, ranges_main, recgrad, colour_parts, dF_parts;
     size_t rec_sun, tiles_sun, counts_sun, offs_sun, qk_a, qv_a, qk_b, qv_b, ranges_sun;
     size_t sun_depth, bounds, radix_temp, tmask_sun, cmask, cmask_bytes, stat_main, stat_sun;
+    size_t torder_main, torder_sun, torder_parts;
     size_t inv_order, vis_rank;
     size_t geom_seeds, geom_cams, geom_parts;
     size_t total;
@@ -108,6 +109,8 @@ struct ss_plan {
     uint32_t *order_main = nullptr, *order_sun = nullptr;
     bool sun_order_shared = false;   // the last shadow pass used the main-view order buffers
     uint32_t *lists_main = nullptr, *lists_sun = nullptr;
+    // raster dispatch orders built with the current binning (null: static XCD order)
+    const uint32_t *torder_main = nullptr, *torder_sun = nullptr;
     template <class T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
 
@@ -223,6 +226,10 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     // forward -> backward contributor masks of 8x8 tiles (other sizes use the box test)
     L.cmask_bytes = p->st.tile_size == 8 ? cmask_words(cm, p->tiles_main_max) * 8 : 0;
     L.cmask = take(L.cmask_bytes);
+    // heavy-first raster dispatch orders and their per-XCD block counts
+    L.torder_main = take((size_t)p->tiles_main_max * 4);
+    L.torder_sun = take((size_t)p->tiles_sun_max * 4);
+    L.torder_parts = take(((size_t)8 * tile_order_blocks(std::max(p->tiles_main_max, p->tiles_sun_max)) + 8) * 4);
     // normal-consistency loss: per-pixel depth-adjoint seeds, per-view cameras, block sums
     L.geom_seeds = take((size_t)p->P * 8);
     L.geom_cams = take(nv * sizeof(GeomCam));
@@ -248,6 +255,8 @@ static ss_status check_settings(const ss_raster_settings *s)
         return fail(SS_ERR_INVALID_ARG, "threshold setting out of range");
     if (s->sun_map_size < 8 || s->sun_map_size > 16384)
         return fail(SS_ERR_INVALID_ARG, "sun_map_size must be in [8, 16384]");
+    if (s->tile_order != 0 && s->tile_order != 1)
+        return fail(SS_ERR_INVALID_ARG, "tile_order must be 0 or 1");
     return SS_OK;
 }
 
@@ -364,6 +373,14 @@ static ss_status bin_views(ss_plan *p, const ss_views *v, bool sun, const uint32
                             p->at<void>(L.radix_temp), &in_b, st, &seg));
     uint32_t *lists = in_b ? vb : va;
     if (sun) p->lists_sun = lists; else p->lists_main = lists;
+    const uint32_t *torder = nullptr;
+    if (p->st.tile_order == 1) {
+        uint32_t *o = p->at<uint32_t>(sun ? L.torder_sun : L.torder_main);
+        SS_HIP(launch_tile_order(p->at<uint32_t>(sun ? L.ranges_sun : L.ranges_main), ntiles,
+                                 counters + (sun ? 1 : 0), !sun, o, p->at<uint32_t>(L.torder_parts), st));
+        torder = o;
+    }
+    if (sun) p->torder_sun = torder; else p->torder_main = torder;
     return SS_OK;
 }
 
@@ -490,6 +507,7 @@ void ss_default_settings(ss_raster_settings *out)
     out->esm_c = 2.0f;
     out->esm_bias = 0.5f;
     out->sun_map_size = 1024;
+    out->tile_order = 0;
 }
 
 ss_status ss_context_create(int32_t device, ss_context **out)
@@ -669,7 +687,8 @@ static ss_status forward_pass(ss_plan *p, const ss_surfels *s, const ss_views *v
     SS_HIP(fill_u32(reinterpret_cast<uint32_t *>(stat), 0u, 2 * kStatSlots * kStatStride, st));
     if (!order && (e = prepare(p, s, v, false, &order, &sorted, st)) != SS_OK) return e;
     if ((e = bin_views(p, v, false, order, sorted, vis, true, st)) != SS_OK) return e;
-    const RasterConsts rc = consts(p->st);
+    RasterConsts rc = consts(p->st);
+    rc.torder = p->torder_main;
     {
         StageScope scope(p, SS_STAGE_RASTER_FWD, st);
         SS_HIP(launch_raster_fwd(p->st.tile_size, false, vis != nullptr, p->tiles_main, p->nv,
@@ -743,7 +762,8 @@ static ss_status backward_pass(ss_plan *p, const ss_surfels *s, const ss_views *
         return fail(SS_ERR_INVALID_ARG, "a gradient output is NULL");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const Layout &L = p->L;
-    const RasterConsts rc = consts(p->st);
+    RasterConsts rc = consts(p->st);
+    rc.torder = p->torder_main;
     float *recgrad = p->at<float>(L.recgrad);
     {
         StageScope scope(p, SS_STAGE_REDUCE, st);
@@ -850,7 +870,8 @@ static ss_status shadow_pass(ss_plan *p, const ss_surfels *s, const ss_views *v,
     }
     if ((e = bin_views(p, v, true, order, sorted, nullptr, true, st)) != SS_OK) return e;
     float *D = sun_depth ? sun_depth : p->at<float>(L.sun_depth);
-    const RasterConsts rc = consts(p->st);
+    RasterConsts rc = consts(p->st);
+    rc.torder = p->torder_sun;
     {
         StageScope scope(p, SS_STAGE_SUN_RASTER, st);
         SS_HIP(launch_raster_fwd(p->st.tile_size, true, false, p->tiles_sun, p->nv,
@@ -1311,7 +1332,8 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
     }
     if ((e = bin_views(p, v, true, order, sorted, nullptr, true, st, tmask)) != SS_OK) return e;
     float *D = sun_depth ? sun_depth : p->at<float>(L.sun_depth);
-    const RasterConsts rc = consts(p->st);
+    RasterConsts rc = consts(p->st);
+    rc.torder = p->torder_sun;
     {
         StageScope scope(p, SS_STAGE_SUN_RASTER, st);
         SS_HIP(launch_raster_fwd(p->st.tile_size, true, false, p->tiles_sun, p->nv,

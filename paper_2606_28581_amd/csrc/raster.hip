@@ -390,6 +390,129 @@ hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ tile dispatch order
+// Block b of a raster launch runs on XCD b % 8 as that XCD's (b / 8)-th block.  XCD x
+// owns the blocks b = 8 i + x, i < n_x, and xcd_tile<CHUNKED>(b) names the tile each one
+// rasterizes; the order below keeps that tile set per XCD and renumbers i so that the
+// heavy tiles (list length >= 2 x mean) come first.  Three passes over (x, block of
+// kOrdBlock consecutive i): count heavy tiles, scan the counts per XCD, write.
+constexpr int kOrdBlock = 1024;
+
+int tile_order_blocks(int32_t ntiles)
+{
+    const int per_xcd = (ntiles + 7) / 8;
+    return (per_xcd + kOrdBlock - 1) / kOrdBlock;
+}
+
+template <bool CHUNKED>
+__device__ __forceinline__ bool heavy_tile(const uint32_t *ranges, int32_t ntiles,
+                                           unsigned long long total, int x, int i, int &tile)
+{
+    const int b = 8 * i + x;
+    if (b >= ntiles) { tile = -1; return false; }
+    tile = xcd_tile<CHUNKED>(b, ntiles);
+    const uint64_t len = ranges[2 * tile + 1] - ranges[2 * tile];
+    // len >= 2 total / ntiles without division
+    return len * (uint64_t)ntiles >= 2ull * total && len > 0;
+}
+
+template <bool CHUNKED>
+__global__ __launch_bounds__(kOrdBlock) void k_order_count(const uint32_t *__restrict__ ranges,
+                                                           int32_t ntiles,
+                                                           const unsigned long long *__restrict__ total,
+                                                           uint32_t *__restrict__ parts)
+{
+    __shared__ uint32_t wsum[kOrdBlock / 64];
+    const int x = blockIdx.y, i = blockIdx.x * kOrdBlock + threadIdx.x;
+    int tile;
+    const bool h = heavy_tile<CHUNKED>(ranges, ntiles, *total, x, i, tile);
+    const uint64_t bal = __ballot(h);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kOrdBlock / 64; ++w) s += wsum[w];
+        parts[x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// One block per XCD: exclusive scan of its block counts in place; parts[8 nblk + x] gets
+// the XCD's heavy total.
+__global__ __launch_bounds__(256) void k_order_scan(uint32_t *__restrict__ parts, int nblk)
+{
+    __shared__ uint32_t carry;
+    __shared__ uint32_t wsum[4];
+    const int x = blockIdx.x;
+    uint32_t *p = parts + (size_t)x * nblk;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblk; base += 256) {
+        const int k = base + threadIdx.x;
+        const uint32_t v = k < nblk ? p[k] : 0u;
+        // inclusive scan within the wave, then across the 4 waves
+        uint32_t inc = v;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int q = 0; q < w; ++q) before += wsum[q];
+        if (k < nblk) p[k] = before + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry = before + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[(size_t)8 * nblk + x] = carry;
+}
+
+template <bool CHUNKED>
+__global__ __launch_bounds__(kOrdBlock) void k_order_write(const uint32_t *__restrict__ ranges,
+                                                           int32_t ntiles,
+                                                           const unsigned long long *__restrict__ total,
+                                                           const uint32_t *__restrict__ parts,
+                                                           uint32_t *__restrict__ order)
+{
+    __shared__ uint32_t wsum[kOrdBlock / 64];
+    const int x = blockIdx.y, i = blockIdx.x * kOrdBlock + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int tile;
+    const bool h = heavy_tile<CHUNKED>(ranges, ntiles, *total, x, i, tile);
+    const uint64_t bal = __ballot(h);
+    if (lane == 0) wsum[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = parts[x * gridDim.x + blockIdx.x];
+    for (int q = 0; q < w; ++q) before += wsum[q];
+    before += (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));   // heavy tiles before i
+    if (tile < 0) return;
+    const uint32_t heavy_total = parts[(size_t)8 * gridDim.x + x];
+    const uint32_t ni = h ? before : heavy_total + ((uint32_t)i - before);
+    order[8 * (size_t)ni + x] = (uint32_t)tile;
+}
+
+hipError_t launch_tile_order(const uint32_t *ranges, int32_t ntiles,
+                             const unsigned long long *total_pairs, bool chunked,
+                             uint32_t *order, uint32_t *parts, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const int nblk = tile_order_blocks(ntiles);
+    const dim3 grid((unsigned)nblk, 8);
+    if (chunked)
+        hipLaunchKernelGGL(k_order_count<true>, grid, dim3(kOrdBlock), 0, st, ranges, ntiles, total_pairs, parts);
+    else
+        hipLaunchKernelGGL(k_order_count<false>, grid, dim3(kOrdBlock), 0, st, ranges, ntiles, total_pairs, parts);
+    hipLaunchKernelGGL(k_order_scan, dim3(8), dim3(256), 0, st, parts, nblk);
+    if (chunked)
+        hipLaunchKernelGGL(k_order_write<true>, grid, dim3(kOrdBlock), 0, st, ranges, ntiles, total_pairs,
+                           parts, order);
+    else
+        hipLaunchKernelGGL(k_order_write<false>, grid, dim3(kOrdBlock), 0, st, ranges, ntiles, total_pairs,
+                           parts, order);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ per-pair evaluation
 // The same FP32 sequence runs in the forward and the backward so both take the same
 // discrete decisions (skip, stop, branch).
@@ -489,7 +612,8 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     constexpr bool CM = TS == 8 && !DEPTH_ONLY;
     extern __shared__ float4 lds[];
     // sun maps are equal in size and even in work: one contiguous run of tiles per XCD
-    const int tile = xcd_tile<!DEPTH_ONLY>((int)blockIdx.x, (int)gridDim.x);
+    const int tile = rc.torder ? (int)rc.torder[blockIdx.x]
+                               : xcd_tile<!DEPTH_ONLY>((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
     const ViewDesc vd = views[v];
     const int lt = tile - vd.tile_off;
@@ -1021,7 +1145,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + min(rc.batch, NT) * kRecVec4);
     float(*red)[16] = reinterpret_cast<float(*)[16]>(lds_idx + min(rc.batch, NT));
     int &max_last = *reinterpret_cast<int *>(red + NW);
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tile = rc.torder ? (int)rc.torder[blockIdx.x] : xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int v = find_view(views, nv, tile);
     const ViewDesc vd = views[v];
     const int lt = tile - vd.tile_off;

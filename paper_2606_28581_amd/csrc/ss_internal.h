@@ -81,6 +81,9 @@ struct RasterConsts {
     float esm_c, esm_bias;
     float two_inv_s2;   // 2 inv_s2, a kernel argument so that loops read it from an SGPR
     double alpha_min_d, sigma_d, det_rel_eps_d;
+    // dispatch order of the raster kernels: block b rasterizes tile torder[b] (a
+    // permutation from launch_tile_order), or xcd_tile(b) when null
+    const uint32_t *torder;
 };
 
 // Depth-distortion channel of the view raster (the 2DGS squared form of the distortion
@@ -126,6 +129,16 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
     const int x = bid % kXcd, i = bid / kXcd;
     return ((i / kXcdChunk) * kXcd + x) * kXcdChunk + i % kXcdChunk;
 }
+
+// Heavy tiles first (longest-processing-time-first, in two classes): keeps every tile on
+// the XCD that xcd_tile<CHUNKED> gives it, and reorders each XCD's blocks so that its
+// tiles with at least twice the mean list length (total_pairs / ntiles) run first, each
+// class in its original order.  order[b] = tile for block b; parts holds
+// 8 * tile_order_blocks(ntiles) + 8 words.
+int tile_order_blocks(int32_t ntiles);
+hipError_t launch_tile_order(const uint32_t *ranges, int32_t ntiles,
+                             const unsigned long long *total_pairs, bool chunked,
+                             uint32_t *order, uint32_t *parts, hipStream_t st);
 
 // ------------------------------------------------------------------- launchers
 // sort.hip

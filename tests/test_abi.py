@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    assert C.sizeof(_lib.RasterSettings) == 4 * 12
+    assert C.sizeof(_lib.RasterSettings) == 4 * 13
     assert C.sizeof(_lib.Surfels) == 8 * 7
     assert C.sizeof(_lib.Views) == 8 * 10
 
@@ -39,6 +39,7 @@ def test_default_settings_are_the_documented_readings():
     assert s.T_min == pytest.approx(1e-4)
     assert s.lowpass_sigma == pytest.approx(0.70710678)
     assert s.sun_map_size == 1024
+    assert s.tile_order == 0
 
 
 def test_invalid_arguments_fail_without_a_device():

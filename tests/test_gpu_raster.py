@@ -11,6 +11,7 @@ import torch
 
 import oracle
 import synth
+import paper_2606_28581_amd as ss
 from gpu_common import (ATOMIC_ORDER_TOL, GRAD_KEYS, context, expand3, make_plan, oracle_settings, rel_err,
                         to_np)
 
@@ -327,3 +328,37 @@ def test_pair_count_scan_beyond_one_pass_of_the_partials_kernel():
     for v in (0, 17, 39):
         np.testing.assert_array_equal(b["tiles"][v], per_view[v])
     assert b["lists"].shape[0] == expect
+
+
+@pytest.mark.parametrize("ts", [8, 16])
+def test_heavy_first_tile_order_changes_no_pixel(ts):
+    """The heavy-tiles-first dispatch order against the static XCD order (default): every
+    forward output and sun-depth texel bit-identical, gradients equal up to the atomics'
+    summation order (the parity bar).  Two views of 600 x 520 px give more than one 4096-tile round of
+    XCD chunks at 8 x 8."""
+    sc = synth.make_scene(synth.tiny(n_surfels=4000, views=((600, 520), (520, 600)), extent=60.0,
+                                     n_boxes=6, seed=15))
+    res = {}
+    for order in (0, 1):
+        surf, views = ss.scene_to_device(sc, with_sun=True)
+        st = ss.default_settings(tile_size=ts, batch_depth=64, sun_map_size=256, tile_order=order)
+        plan = ss.Plan(context(), surf.mean.shape[0], views.width, views.height, st)
+        plan.ensure_capacity(surf, views)
+        D = torch.empty(2, 256, 256, device="cuda")
+        vis = plan.shadow(surf, views, sun_depth=D)
+        out = plan.forward(surf, views, vis)
+        dI, dD, dN = [torch.as_tensor(x, device="cuda") for x in synth.upstream_grads(sc)]
+        g = plan.backward(surf, views, out, dI, dD, dN, vis=vis)
+        res[order] = ({k: to_np(v) for k, v in out.items()}, to_np(D), to_np(vis),
+                      {k: to_np(v) for k, v in g.items()})
+    (o0, D0, v0, g0), (o1, D1, v1, g1) = res[0], res[1]
+    for k in o0:
+        np.testing.assert_array_equal(o1[k], o0[k], err_msg=k)
+    np.testing.assert_array_equal(D1, D0)
+    np.testing.assert_array_equal(v1, v0)
+    # the gradients' float atomics sum in a different order: held to the parity bar
+    # (rel 1e-3); measured 1.1e-4 on t_u at tile 8
+    for k in GRAD_KEYS:
+        err = rel_err(g1[k], g0[k])
+        print(f"tile order 0 vs 1, ts {ts}: {k} {err:.2e}")
+        assert err < 1e-3, k
