@@ -449,7 +449,9 @@ ss_status ss_mlp_adam(float *w, float *m, float *v, const float *g, int64_t n, f
 /* Surrogate shadow pass: vis[v,k] = sigmoid(MLP(p_k, sun_v)) for every view and surfel;
  * points with |vis - 0.5| < band fall back to the geometric pass (ss_shadow_plain's
  * definition), rasterizing only the sun-map tiles their 3x3 windows touch.  Requires
- * views->sun.  The number of fallback points is reported by ss_plan_stats ([6]). */
+ * views->sun.  The number of fallback points is reported by ss_plan_stats ([6]).  With
+ * band == 0 only the network runs: no sun camera, binning or raster, and sun_depth is
+ * not written. */
 ss_status ss_shadow_surrogate(ss_plan *plan, ss_mlp *mlp, const float *w, const ss_surfels *s,
                               const ss_views *v, float band, float *vis, float *sun_depth,
                               ss_stream stream);

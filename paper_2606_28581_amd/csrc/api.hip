@@ -1313,6 +1313,8 @@ ss_status ss_shadow_surrogate(ss_plan *p, ss_mlp *mlp, const float *w, const ss_
                                   v->sun, p->n * (int64_t)p->nv, p->n, mlp_norm(mlp), true, vis,
                                   nullptr, nullptr, st));
     }
+    // band 0: no point can fall back, the network's output is the whole pass
+    if (band == 0.f) return SS_OK;
     uint32_t *order;
     float *sorted;
     if ((e = prepare(p, s, v, true, &order, &sorted, st)) != SS_OK) return e;
