@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
             const int lim = row_last - (bb + c0);        // chunk records j < lim can contribute
             m &= lim >= 64 ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
             // row-uniform walk, highest position first
-            while (__ballot(m != 0) != 0) {
+            if (__ballot(m != 0) != 0) do {
                 const bool act = m != 0;
                 const int jl = act ? 63 - (int)__builtin_clzll(m) : 0;
                 const int j = c0 + jl;
@@ -1287,16 +1287,20 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                     contrib = act && bb + j < mylast && px >= xlo && px <= xhi && py >= ylo &&
                               py <= yhi && e.alpha >= rc.alpha_min;
                 }
-                float gr[16];
-                pair_gradients<DIST>(e, contrib, r2, r3, r4, r5, pa, dp, HAS_VIS, inv_s2,
-                                     rc.alpha_max, da.ds, Tr, gS, gr);
+                // a step where no lane of the wave contributes changes nothing (a branch
+                // around the rest, and the loop test at the bottom, keep a single back edge:
+                // no register copies per step)
                 const uint64_t cb = __ballot(contrib);
-                if (cb == 0) continue;
-                const float sum = row_transpose_reduce16(gr, lane);
-                // lane i of a row holds value i of its record's 16-lane sum
-                if (((cb >> (quad * 16)) & 0xFFFFull) != 0)
-                    atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane & 15), sum);
-            }
+                if (cb != 0) {
+                    float gr[16];
+                    pair_gradients<DIST>(e, contrib, r2, r3, r4, r5, pa, dp, HAS_VIS, inv_s2,
+                                         rc.alpha_max, da.ds, Tr, gS, gr);
+                    const float sum = row_transpose_reduce16(gr, lane);
+                    // lane i of a row holds value i of its record's 16-lane sum
+                    if (((cb >> (quad * 16)) & 0xFFFFull) != 0)
+                        atomicAdd(gv + (size_t)lds_idx[j] * kGradFloats + (lane & 15), sum);
+                }
+            } while (__ballot(m != 0) != 0);
         }
     }
 #undef SS_FETCH_BWD
