@@ -1050,45 +1050,49 @@ __device__ __forceinline__ DistPixel pixel_distortion_state(bool inside, int64_t
     return d;
 }
 
-// Gradients of one (record, pixel) pair in the back-to-front walk.  Updates the pixel's
-// transmittance Tr and suffix gS when the pair contributes, returns the 16 record
-// gradient values in gr (zero when it does not).
-//
-// The branch of the pair (ub: the surfel's own Gaussian, else the low-pass disk) enters
-// once, by zeroing u (and the depth gradient that flows into u) on the low-pass branch:
-// z = z0 - k . u then equals the centre depth z0, and every u-branch term (the k and Q
-// gradients, the centre gradient through Q) vanishes by multiplication; the low-pass
-// term of the centre gradient is zeroed on the u branch the same way.  With
-// rho2 = d alpha / d rho * 2 = -oG dal (unclamped), the centre gradient is
-//   dL/dc = -(Q^T dL/du + delta rho2 / sigma^2 [low-pass branch]).
+// Per-pair terms of the walk: 1 / (1 - alpha), the pair's depth z (the centre depth on
+// the low-pass branch), g . f (the upstream gradient dotted with the pair's composited
+// features, plus the distortion's d dist / d w term) and the depth gradient per unit
+// weight; u zeroed on the low-pass branch.
+struct PairTerms {
+    float rom, z, gf, gDe, u0, u1;
+};
+
 template <bool DIST>
-__device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, float4 r2,
-                                               float4 r3, float4 r4, float4 r5,
-                                               const PixelAdjoint &pa, const DistPixel &dp,
-                                               bool has_vis, float inv_s2, float alpha_max,
-                                               float ds, float &Tr, float &gS, float (&gr)[16])
+__device__ __forceinline__ PairTerms pair_terms(const PairEval &e, float4 r3, float4 r4, float4 r5,
+                                                const PixelAdjoint &pa, const DistPixel &dp,
+                                                bool has_vis, float ds)
 {
-    // gradient arithmetic with explicit fused multiply-adds (the discrete decisions -
-    // contrib, ub, unclamped - come from eval_pair and the forward's own tests)
-    const float rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
-    const float Tb = Tr * rom;
-    const float w = contrib ? e.alpha * Tb : 0.f;
-    const float u0 = e.ub ? e.u0 : 0.f, u1 = e.ub ? e.u1 : 0.f;
-    const float z = __fmaf_rn(-r3.z, u0, __fmaf_rn(-r3.w, u1, r3.y));
-    float gf = fmaf(pa.gA0, r4.x, fmaf(pa.gA1, r4.y, fmaf(pa.gA2, r4.z, fmaf(pa.gD, z,
+    PairTerms t;
+    t.rom = __builtin_amdgcn_rcpf(1.f - e.alpha);
+    t.u0 = e.ub ? e.u0 : 0.f;
+    t.u1 = e.ub ? e.u1 : 0.f;
+    t.z = __fmaf_rn(-r3.z, t.u0, __fmaf_rn(-r3.w, t.u1, r3.y));
+    float gf = fmaf(pa.gA0, r4.x, fmaf(pa.gA1, r4.y, fmaf(pa.gA2, r4.z, fmaf(pa.gD, t.z,
                fmaf(pa.gN0, r5.x, fmaf(pa.gN1, r5.y, pa.gN2 * r5.z))))));
     if (has_vis) gf = fmaf(pa.gV, r4.w, gf);
     float gDe = pa.gD;
     if (DIST) {
         // d dist / d w_k = sum_j w_j (m'_k - m'_j)^2, d dist / d m_k = 2 w_k sum_j w_j (m'_k - m'_j)
-        const float mp = (z - dp.zref) * ds;
+        const float mp = (t.z - dp.zref) * ds;
         gf = fmaf(dp.gDist, fmaf(mp, fmaf(mp, dp.At, -2.f * dp.M1), dp.M2), gf);
         gDe = fmaf(2.f * dp.gDist * ds, fmaf(mp, dp.At, -dp.M1), pa.gD);
     }
-    const float dal = contrib ? fmaf(Tb, gf, -gS * rom) : 0.f;
-    gS = fmaf(w, gf, gS);
-    Tr = contrib ? Tb : Tr;
-    const float dz = w * gDe;
+    t.gf = gf;
+    t.gDe = gDe;
+    return t;
+}
+
+// The 16 record-gradient values of one pair from its weight w, dL/dalpha and dL/dz.
+// The pair's branch enters once, through u (zero on the low-pass branch): the k, Q and
+// u-centre terms vanish by multiplication, and the low-pass term of the centre gradient
+// is zeroed on the u branch.  With rho2 = -oG dal (unclamped),
+//   dL/dc = -(Q^T dL/du + delta rho2 / sigma^2 [low-pass branch]).
+__device__ __forceinline__ void pair_record_grads(const PairEval &e, float w, float dal, float dz,
+                                                  float u0, float u1, float4 r2, float4 r3,
+                                                  const PixelAdjoint &pa, float inv_s2,
+                                                  float alpha_max, float (&gr)[16])
+{
     const float dzu = e.ub ? dz : 0.f;
     gr[G_AR] = w * pa.gA0; gr[G_AG] = w * pa.gA1; gr[G_AB] = w * pa.gA2;
     gr[G_NX] = w * pa.gN0; gr[G_NY] = w * pa.gN1; gr[G_NZ] = w * pa.gN2;
@@ -1107,6 +1111,25 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
     const float nfd = e.ub ? 0.f : -(inv_s2 * rho2);
     gr[G_CX] = fmaf(-r2.x, du0, fmaf(-r2.z, du1, e.dx * nfd));
     gr[G_CY] = fmaf(-r2.y, du0, fmaf(-r2.w, du1, e.dy * nfd));
+}
+
+// Gradients of one (record, pixel) pair in the sequential back-to-front walk.  Updates
+// the pixel's transmittance Tr and suffix gS when the pair contributes, returns the 16
+// record gradient values in gr (zero when it does not).
+template <bool DIST>
+__device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, float4 r2,
+                                               float4 r3, float4 r4, float4 r5,
+                                               const PixelAdjoint &pa, const DistPixel &dp,
+                                               bool has_vis, float inv_s2, float alpha_max,
+                                               float ds, float &Tr, float &gS, float (&gr)[16])
+{
+    const PairTerms t = pair_terms<DIST>(e, r3, r4, r5, pa, dp, has_vis, ds);
+    const float Tb = Tr * t.rom;
+    const float w = contrib ? e.alpha * Tb : 0.f;
+    const float dal = contrib ? fmaf(Tb, t.gf, -gS * t.rom) : 0.f;
+    gS = fmaf(w, t.gf, gS);
+    Tr = contrib ? Tb : Tr;
+    pair_record_grads(e, w, dal, w * t.gDe, t.u0, t.u1, r2, r3, pa, inv_s2, alpha_max, gr);
 }
 
 // --------------------------------------------------------------- raster backward
@@ -1306,6 +1329,237 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
 #undef SS_FETCH_BWD
 }
 
+// ------------------------------------------------- raster backward, 8x8 tiles
+// Record-parallel rows.  With the forward's contributor masks the four 4x4 quadrants of
+// an 8x8 tile are walked one after another, and all four 16-lane rows of the wave work
+// on the *same* quadrant: lane i of every row holds pixel i of the quadrant, and each
+// step takes the next four records of the quadrant's walk (the union of its 16 pixels'
+// masks, back to front), one per row.  The pixel recursion of Eq. rasterization runs
+// across the rows: with rom = 1 / (1 - alpha) for a contributing pair (1 otherwise) and
+// x = w (g . f), row r needs T before its record = T_cur * prod_{k <= r} rom_k and the
+// suffix g . S = gS_cur + sum_{k < r} x_k; both are scans over the four rows, done
+// lane-wise with two lane swaps each (rows 0<->1, 2<->3, then 0,1<->2,3), which also
+// give the totals that advance T_cur and gS_cur.  A step costs ~10 % more VALU than the
+// quadrant-per-row walk but the walk takes sum_q |U_q| / 4 steps instead of
+// sum over chunks of max_q |U_q|, a third fewer on the 2M-surfel views.  Per-pixel state
+// (the adjoint inputs, T, the suffix, the distortion totals) lives in LDS between
+// quadrants.
+constexpr int kPstBase = 10, kPstDist = 5;
+
+__device__ __forceinline__ float swap16_lo_hi(float v, float &hi)
+{
+    // rows [v0, v1, v2, v3] -> lo = [v0, v0, v2, v2], hi = [v1, v1, v3, v3]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    hi = __uint_as_float(r[1]);
+    return __uint_as_float(r[0]);
+}
+
+__device__ __forceinline__ float swap32_lo_hi(float v, float &hi)
+{
+    // rows [v0, v1, v2, v3] -> lo = [v0, v1, v0, v1], hi = [v2, v3, v2, v3]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    hi = __uint_as_float(r[1]);
+    return __uint_as_float(r[0]);
+}
+
+// Inclusive product over rows 0..r (per lane position), and the product of all four.
+__device__ __forceinline__ float rows_prefix_mul(float f, bool odd, bool upper, float &total)
+{
+    float b;
+    const float a = swap16_lo_hi(f, b);
+    const float pair = a * b;                       // f0 f1 in rows 0, 1; f2 f3 in rows 2, 3
+    const float p1 = odd ? pair : a;
+    float d;
+    const float c = swap32_lo_hi(pair, d);          // c = f0 f1, d = f2 f3 in every row
+    total = c * d;
+    return upper ? p1 * c : p1;
+}
+
+// Inclusive sum over rows 0..r, and the sum of all four.
+__device__ __forceinline__ float rows_prefix_add(float x, bool odd, bool upper, float &total)
+{
+    float b;
+    const float a = swap16_lo_hi(x, b);
+    const float pair = a + b;
+    const float p1 = odd ? pair : a;
+    float d;
+    const float c = swap32_lo_hi(pair, d);
+    total = c + d;
+    return upper ? p1 + c : p1;
+}
+
+template <bool HAS_VIS, bool DIST>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_raster_bwd_rp(
+    int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
+    const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
+    RasterConsts rc, const float *__restrict__ colC, const float *__restrict__ colc,
+    const float *__restrict__ amb, const float *__restrict__ Ain,
+    const float *__restrict__ Vin, const float *__restrict__ Tin,
+    const int32_t *__restrict__ lastin, const float *__restrict__ dI,
+    const float *__restrict__ dD, const float *__restrict__ dN, float *__restrict__ recgrad,
+    float *__restrict__ colour_partials, const unsigned long long *__restrict__ cmask,
+    DistArgs da)
+{
+    constexpr int kPst = kPstBase + (DIST ? kPstDist : 0);
+    // LDS: staged records (64 x 6 float4, a record's address is one multiply), their
+    // ranks, the contributor words of the chunk, per-pixel state [field][pixel], the
+    // quadrant's walk list, the tile's largest `last`
+    extern __shared__ float4 lds[];
+    uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + 64 * kRecVec4);
+    unsigned long long *ownw = reinterpret_cast<unsigned long long *>(lds_idx + 64);
+    float *pst = reinterpret_cast<float *>(ownw + 64);
+    uint32_t *qlist = reinterpret_cast<uint32_t *>(pst + kPst * 64);
+    int &max_last = *reinterpret_cast<int *>(qlist + 64);
+    const int tile = rc.torder ? (int)rc.torder[blockIdx.x] : xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int v = find_view(views, nv, tile);
+    const ViewDesc vd = views[v];
+    const int lt = tile - vd.tile_off;
+    const int tx = lt % vd.tiles_x, ty = lt / vd.tiles_x;
+    const int lane = threadIdx.x;
+    const int wx0 = tx * 8, wy0 = ty * 8;
+    const int row = lane >> 4, li = lane & 15;
+    const bool odd = lane & 16, upper = lane & 32;
+    // prologue in the owner mapping: lane 16 q + i holds pixel i of quadrant q
+    const int opx = wx0 + 4 * (row & 1) + (li & 3), opy = wy0 + 4 * (row >> 1) + (li >> 2);
+    const bool inside = opx < vd.W && opy < vd.H;
+    const int64_t P = (int64_t)vd.W * vd.H;
+    const int64_t local = (int64_t)opy * vd.W + opx;
+    const int64_t g = vd.pix_off + local;
+    const int64_t b3 = 3 * vd.pix_off + local;
+    if (lane == 0) max_last = 0;
+    qlist[lane] = 0u;
+    float cg[16];
+    {
+        const PixelAdjoint pa = pixel_adjoint<HAS_VIS>(inside, v, g, b3, P, colC, colc, amb, Ain, Vin,
+                                                       Tin, lastin, dI, dD, dN, cg);
+        const float s = wave_transpose_reduce16(cg, lane);
+        if ((lane & 3) == 0) colour_partials[(int64_t)tile * 16 + (lane >> 2)] = s;
+        pst[0 * 64 + lane] = pa.gA0; pst[1 * 64 + lane] = pa.gA1; pst[2 * 64 + lane] = pa.gA2;
+        pst[3 * 64 + lane] = pa.gV;  pst[4 * 64 + lane] = pa.gD;
+        pst[5 * 64 + lane] = pa.gN0; pst[6 * 64 + lane] = pa.gN1; pst[7 * 64 + lane] = pa.gN2;
+        pst[8 * 64 + lane] = pa.Tr;  pst[9 * 64 + lane] = 0.f;
+        if (DIST) {
+            const DistPixel dp = pixel_distortion_state(inside, g, pa.Tr, da);
+            pst[10 * 64 + lane] = dp.gDist; pst[11 * 64 + lane] = dp.zref;
+            pst[12 * 64 + lane] = dp.At;    pst[13 * 64 + lane] = dp.M1;
+            pst[14 * 64 + lane] = dp.M2;
+        }
+        if (pa.last > 0) atomicMax(&max_last, pa.last);
+    }
+    __syncthreads();
+    const uint32_t start = ranges[2 * tile];
+    const int tile_len = (int)(ranges[2 * tile + 1] - start);
+    const float4 *recv = rec + (size_t)v * (size_t)n * kRecStride4;
+    float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
+    const int batch = min(rc.batch, 64);
+    const float inv_s2 = rc.two_inv_s2 * 0.5f;
+    const int blk_last = min(max_last, tile_len);
+    const size_t wbase = (size_t)(start >> 6) + (size_t)tile;
+    const int pidx = ((opy - wy0) << 3) | (opx - wx0);
+    float4 q0, q1, q2, q3, q4, q5;
+    uint32_t qidx = 0;
+#define SS_FETCH_RP(BB, CNT)                                                           \
+    if (lane < (CNT)) {                                                                \
+        qidx = min(lists[start + (BB) + lane], (uint32_t)(n - 1));                     \
+        const float4 *src_ = recv + (size_t)qidx * kRecStride4;                        \
+        q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3]; q4 = src_[4]; q5 = src_[5]; \
+    }
+    const int nbat = (blk_last + batch - 1) / batch;
+    if (nbat > 0) {
+        const int bb0 = (nbat - 1) * batch;
+        SS_FETCH_RP(bb0, blk_last - bb0);
+    }
+    for (int kb = nbat - 1; kb >= 0; --kb) {
+        const int bb = kb * batch;
+        const int nb = min(bb + batch, blk_last) - bb;
+        __syncthreads();
+        if (lane < nb) {
+            float4 *dst = lds + lane * kRecVec4;
+            dst[0] = q0; dst[1] = q1; dst[2] = q2; dst[3] = q3; dst[4] = q4; dst[5] = q5;
+            lds_idx[lane] = qidx;
+        }
+        // this lane's pixel's forward mask over the batch's positions [bb, bb + nb)
+        uint64_t own = 0;
+        {
+            const int sh = bb & 63;
+            const unsigned long long *wp = cmask + (wbase + (bb >> 6)) * 64 + pidx;
+            if (inside) {
+                own = wp[0] >> sh;
+                if (sh != 0 && sh + nb > 64) own |= wp[64] << (64 - sh);
+            }
+            own &= nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+        }
+        ownw[lane] = own;
+        const uint64_t un = row_or64(own);          // row q: the union of quadrant q
+        __syncthreads();
+        if (kb > 0) SS_FETCH_RP(bb - batch, batch);
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t U = ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(un >> 32), 16 * q) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)un, 16 * q);
+            if (U == 0) continue;                     // uniform
+            const int nq = __popcll(U);
+            // walk list of the quadrant: position of the k-th set bit from the top
+            {
+                const bool set = (U >> lane) & 1ull;
+                const int k = lane == 63 ? 0 : __popcll(U >> (lane + 1));
+                if (set) qlist[k] = (uint32_t)lane;
+            }
+            const int p = 16 * q + li;               // the quadrant's pixel of this lane
+            const float gA0 = pst[0 * 64 + p], gA1 = pst[1 * 64 + p], gA2 = pst[2 * 64 + p];
+            const float gV = pst[3 * 64 + p], gD = pst[4 * 64 + p];
+            const float gN0 = pst[5 * 64 + p], gN1 = pst[6 * 64 + p], gN2 = pst[7 * 64 + p];
+            float Tr = pst[8 * 64 + p], gS = pst[9 * 64 + p];
+            DistPixel dp{0, 0, 0, 0, 0};
+            if (DIST) {
+                dp.gDist = pst[10 * 64 + p]; dp.zref = pst[11 * 64 + p]; dp.At = pst[12 * 64 + p];
+                dp.M1 = pst[13 * 64 + p]; dp.M2 = pst[14 * 64 + p];
+            }
+            const uint64_t ownq = ownw[p];
+            const PixelAdjoint pa{gA0, gA1, gA2, gV, gD, gN0, gN1, gN2, Tr, 0};
+            const int qpx = wx0 + 4 * (q & 1) + (li & 3), qpy = wy0 + 4 * (q >> 1) + (li >> 2);
+            const float fx = (float)qpx + 0.5f, fy = (float)qpy + 0.5f;
+            __syncthreads();                         // the walk list is complete
+            for (int s0 = 0; s0 < nq; s0 += 4) {
+                const int k = s0 + row;
+                const bool act = k < nq;
+                const int jl = (int)qlist[k];        // k < 64; stale entries are valid positions
+                const float4 *R = lds + __mul24(jl, kRecVec4);
+                const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
+                const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
+                const bool contrib = act && ((ownq >> jl) & 1ull);
+                const PairTerms t = pair_terms<DIST>(e, r3, r4, r5, pa, dp, HAS_VIS, da.ds);
+                const float f = contrib ? t.rom : 1.f;
+                float ptot;
+                const float Pinc = rows_prefix_mul(f, odd, upper, ptot);
+                const float Tb = Tr * Pinc;          // T before this row's record
+                const float w = contrib ? e.alpha * Tb : 0.f;
+                const float x = w * t.gf;
+                float stot;
+                const float Sinc = rows_prefix_add(x, odd, upper, stot);
+                const float gSb = gS + (Sinc - x);   // g . S after this row's record
+                const float dal = contrib ? fmaf(Tb, t.gf, -gSb * t.rom) : 0.f;
+                Tr *= ptot;
+                gS += stot;
+                const uint64_t cb = __ballot(contrib);
+                if (cb != 0) {
+                    float gr[16];
+                    pair_record_grads(e, w, dal, w * t.gDe, t.u0, t.u1, r2, r3, pa, inv_s2,
+                                      rc.alpha_max, gr);
+                    const float sum = row_transpose_reduce16(gr, lane);
+                    if (((cb >> (row * 16)) & 0xFFFFull) != 0)
+                        atomicAdd(gv + (size_t)lds_idx[jl] * kGradFloats + li, sum);
+                }
+            }
+            if (row == 0) {
+                pst[8 * 64 + p] = Tr;
+                pst[9 * 64 + p] = gS;
+            }
+            __syncthreads();                         // list and state reused by the next quadrant
+        }
+    }
+#undef SS_FETCH_RP
+}
+
 template <int TS, bool HV, bool DIST>
 static void launch_bwd_d(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
                          const ViewDesc *views, const uint32_t *ranges, const uint32_t *lists,
@@ -1317,9 +1571,13 @@ static void launch_bwd_d(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
 {
     if constexpr (TS == 8) {
         if (cmask) {
-            hipLaunchKernelGGL((k_raster_bwd<TS, HV, DIST, true>), grid, dim3(TS * TS), lds, st, nv,
-                               views, ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc,
-                               colC, colc, amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+            constexpr int kPst = kPstBase + (DIST ? kPstDist : 0);
+            const size_t lds_rp = (size_t)64 * (kRecVec4 * sizeof(float4) + sizeof(uint32_t) +
+                                                sizeof(unsigned long long) + kPst * sizeof(float) +
+                                                sizeof(uint32_t)) + sizeof(int);
+            hipLaunchKernelGGL((k_raster_bwd_rp<HV, DIST>), grid, dim3(64), lds_rp, st, nv, views,
+                               ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC,
+                               colc, amb, A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
             return;
         }
     }
