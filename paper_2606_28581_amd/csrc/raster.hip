@@ -1405,8 +1405,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     // ranks, the contributor words of the chunk, per-pixel state [field][pixel], the
     // quadrant's walk list, the tile's largest `last`
     extern __shared__ float4 lds[];
-    uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + 64 * kRecVec4);
-    unsigned long long *ownw = reinterpret_cast<unsigned long long *>(lds_idx + 64);
+    const int batch = min(rc.batch, 64);
+    uint32_t *lds_idx = reinterpret_cast<uint32_t *>(lds + batch * kRecVec4);
+    unsigned long long *ownw = reinterpret_cast<unsigned long long *>(lds_idx + ((batch + 1) & ~1));
     float *pst = reinterpret_cast<float *>(ownw + 64);
     uint32_t *qlist = reinterpret_cast<uint32_t *>(pst + kPst * 64);
     int &max_last = *reinterpret_cast<int *>(qlist + 64);
@@ -1451,7 +1452,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int tile_len = (int)(ranges[2 * tile + 1] - start);
     const float4 *recv = rec + (size_t)v * (size_t)n * kRecStride4;
     float *gv = recgrad + (size_t)v * (size_t)n * kGradFloats;
-    const int batch = min(rc.batch, 64);
     const float inv_s2 = rc.two_inv_s2 * 0.5f;
     const int blk_last = min(max_last, tile_len);
     const size_t wbase = (size_t)(start >> 6) + (size_t)tile;
@@ -1519,10 +1519,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             const int qpx = wx0 + 4 * (q & 1) + (li & 3), qpy = wy0 + 4 * (q >> 1) + (li >> 2);
             const float fx = (float)qpx + 0.5f, fy = (float)qpy + 0.5f;
             __syncthreads();                         // the walk list is complete
+            // record positions are read one step ahead; k < 64, and entries past nq are
+            // stale positions of earlier quadrants, all below the batch size
+            int jl_next = (int)qlist[row];
             for (int s0 = 0; s0 < nq; s0 += 4) {
                 const int k = s0 + row;
                 const bool act = k < nq;
-                const int jl = (int)qlist[k];        // k < 64; stale entries are valid positions
+                const int jl = jl_next;
+                jl_next = (int)qlist[min(k + 4, 63)];
                 const float4 *R = lds + __mul24(jl, kRecVec4);
                 const float4 r0 = R[0], r1 = R[1], r2 = R[2], r3 = R[3], r4 = R[4], r5 = R[5];
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
@@ -1540,15 +1544,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 const float dal = contrib ? fmaf(Tb, t.gf, -gSb * t.rom) : 0.f;
                 Tr *= ptot;
                 gS += stot;
+                // every walked record is composited by some pixel of the quadrant, so each
+                // step has work; a row past the end of the list adds nothing
+                float gr[16];
+                pair_record_grads(e, w, dal, w * t.gDe, t.u0, t.u1, r2, r3, pa, inv_s2,
+                                  rc.alpha_max, gr);
+                const float sum = row_transpose_reduce16(gr, lane);
                 const uint64_t cb = __ballot(contrib);
-                if (cb != 0) {
-                    float gr[16];
-                    pair_record_grads(e, w, dal, w * t.gDe, t.u0, t.u1, r2, r3, pa, inv_s2,
-                                      rc.alpha_max, gr);
-                    const float sum = row_transpose_reduce16(gr, lane);
-                    if (((cb >> (row * 16)) & 0xFFFFull) != 0)
-                        atomicAdd(gv + (size_t)lds_idx[jl] * kGradFloats + li, sum);
-                }
+                if (((cb >> (row * 16)) & 0xFFFFull) != 0)
+                    atomicAdd(gv + (size_t)lds_idx[jl] * kGradFloats + li, sum);
             }
             if (row == 0) {
                 pst[8 * 64 + p] = Tr;
@@ -1572,8 +1576,10 @@ static void launch_bwd_d(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
     if constexpr (TS == 8) {
         if (cmask) {
             constexpr int kPst = kPstBase + (DIST ? kPstDist : 0);
-            const size_t lds_rp = (size_t)64 * (kRecVec4 * sizeof(float4) + sizeof(uint32_t) +
-                                                sizeof(unsigned long long) + kPst * sizeof(float) +
+            const int b = min(rc.batch, 64);
+            const size_t lds_rp = (size_t)b * kRecVec4 * sizeof(float4) +
+                                  (size_t)((b + 1) & ~1) * sizeof(uint32_t) +
+                                  (size_t)64 * (sizeof(unsigned long long) + kPst * sizeof(float) +
                                                 sizeof(uint32_t)) + sizeof(int);
             hipLaunchKernelGGL((k_raster_bwd_rp<HV, DIST>), grid, dim3(64), lds_rp, st, nv, views,
                                ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC,
