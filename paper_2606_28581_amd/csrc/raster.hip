@@ -327,12 +327,15 @@ hipError_t launch_vis_to_rank(const float *vis, int64_t n, int32_t nv, const uin
 constexpr int kEmitThreads = 256;
 constexpr int kEmitStage = 1024;
 
+template <typename KT>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(
     int64_t n, const ViewDesc *__restrict__ views, const short4 *__restrict__ tiles,
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ offsets, uint64_t cap,
-    uint32_t *__restrict__ keys, uint32_t *__restrict__ vals, const uint32_t *__restrict__ tmask)
+    KT *__restrict__ keys, uint32_t *__restrict__ vals, const uint32_t *__restrict__ tmask)
 {
-    __shared__ uint32_t sk[kEmitStage], sv[kEmitStage];
+    constexpr bool kLocal = sizeof(KT) == 2;   // tile id within the view, else global
+    __shared__ KT sk[kEmitStage];
+    __shared__ uint32_t sv[kEmitStage];
     const int v = blockIdx.y;
     const int64_t r0 = (int64_t)blockIdx.x * kEmitThreads;
     const int64_t r = r0 + threadIdx.x;
@@ -350,8 +353,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
             const ViewDesc vd = views[v];
             for (int ty = t.z; ty <= t.w; ++ty)
                 for (int tx = t.x; tx <= t.y; ++tx) {
-                    const uint32_t key = (uint32_t)(vd.tile_off + ty * vd.tiles_x + tx);
-                    if (tmask && tmask[key] == 0u) continue;
+                    const uint32_t lkey = (uint32_t)(ty * vd.tiles_x + tx);
+                    const uint32_t gkey = (uint32_t)vd.tile_off + lkey;
+                    if (tmask && tmask[gkey] == 0u) continue;
+                    const KT key = (KT)(kLocal ? lkey : gkey);
                     if (staged) {
                         const uint64_t l = pos - b_lo;
                         if (l < (uint64_t)kEmitStage) {
@@ -380,13 +385,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(
 
 hipError_t launch_emit(const uint32_t *, int64_t n, int32_t nv, const ViewDesc *views,
                        const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
-                       uint64_t cap, uint32_t *keys, uint32_t *vals, const uint32_t *tmask,
-                       hipStream_t st)
+                       uint64_t cap, void *keys, bool keys16, uint32_t *vals,
+                       const uint32_t *tmask, hipStream_t st)
 {
     if (n <= 0 || cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((n + kEmitThreads - 1) / kEmitThreads), (unsigned)nv),
-                       dim3(kEmitThreads), 0, st, n, views, tiles, counts, offsets, cap, keys, vals,
-                       tmask);
+    const dim3 grid((unsigned)((n + kEmitThreads - 1) / kEmitThreads), (unsigned)nv);
+    if (keys16)
+        hipLaunchKernelGGL(k_emit<uint16_t>, grid, dim3(kEmitThreads), 0, st, n, views, tiles, counts,
+                           offsets, cap, static_cast<uint16_t *>(keys), vals, tmask);
+    else
+        hipLaunchKernelGGL(k_emit<uint32_t>, grid, dim3(kEmitThreads), 0, st, n, views, tiles, counts,
+                           offsets, cap, static_cast<uint32_t *>(keys), vals, tmask);
     return hipGetLastError();
 }
 

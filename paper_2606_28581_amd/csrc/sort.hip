@@ -334,8 +334,19 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_table(
     }
 }
 
+// KT = uint16_t: tile keys local to their segment (the digit is taken from the key
+// itself, the segment base only offsets the tile ranges); uint32_t: keys carry the
+// segment base, which the digit subtracts.
+template <typename KT>
+__device__ __forceinline__ uint32_t key_digit(KT key, uint32_t base, int shift)
+{
+    constexpr bool kLocal = sizeof(KT) == 2;
+    return (((uint32_t)key - (kLocal ? 0u : base)) >> shift) & 255u;
+}
+
+template <typename KT>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
-    const uint32_t *keys, const SegDesc *segs, int nseg, const unsigned long long *n_dev,
+    const KT *keys, const SegDesc *segs, int nseg, const unsigned long long *n_dev,
     int64_t cap, int64_t n_host, int shift, uint32_t *hist)
 {
     __shared__ uint32_t h[256];
@@ -350,14 +361,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             const int64_t i = wbase + it * kWave + lane;
-            key[it] = i < br.hi ? keys[i] : 0u;
+            key[it] = i < br.hi ? (uint32_t)keys[i] : 0u;
         }
         // one LDS add per key: the LDS serialises lanes that hit the same counter, which
         // costs less than finding each digit's group of lanes with ballots
 #pragma unroll
         for (int it = 0; it < kSortItems; ++it) {
             if (wbase + it * kWave + lane < br.hi)
-                atomicAdd(&h[((key[it] - br.base) >> shift) & 255u], 1u);
+                atomicAdd(&h[key_digit<KT>((KT)key[it], br.base, shift)], 1u);
         }
     }
     __syncthreads();
@@ -414,17 +425,20 @@ __global__ __launch_bounds__(kScanPartialsThreads) void k_hist_scan_partials(uin
 // output position of its run: ranges[2k] = min over blocks, ranges[2k + 1] = max + 1.
 // A block holds its items in LDS sorted by the whole key (stable on the top digit of
 // items that the lower passes left sorted), so equal keys are adjacent there.
+template <typename KT>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t *kin, const uint32_t *vin, uint32_t *kout, uint32_t *vout,
+    const KT *kin, const uint32_t *vin, KT *kout, uint32_t *vout,
     const uint32_t *offs, const SegDesc *segs, int nseg, const unsigned long long *n_dev,
     int64_t cap, int64_t n_host, int shift, int nbits, uint32_t *ranges, int64_t nkeys)
 {
+    constexpr bool kLocal = sizeof(KT) == 2;
     __shared__ uint32_t wcnt[kSortWaves][256];
     __shared__ uint32_t wsink[kSortWaves][kWave];  // target of the lanes that are not group leaders
     __shared__ uint32_t dbase[256];          // block-local start of each digit's run
     __shared__ uint32_t gshift[256];         // global start minus local start, per digit
     __shared__ uint32_t lds_w[kSortWaves];
-    __shared__ uint32_t skey[kSortTile], sval[kSortTile];
+    __shared__ KT skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
     const BlockRange br = block_range(segs, nseg, n_dev, cap, n_host, blockIdx.x);
     if (!br.live) return;   // uniform over the block
     for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
@@ -437,7 +451,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t i = wbase + it * kWave + lane;
         const bool valid = i < br.hi;
-        key[it] = valid ? kin[i] : 0u;
+        key[it] = valid ? (uint32_t)kin[i] : 0u;
         val[it] = valid ? vin[i] : 0u;
     }
     // stable ranks: per item row, the lowest lane of each equal-digit group adds the group
@@ -447,7 +461,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const bool valid = wbase + it * kWave + lane < br.hi;
-        const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
+        const uint32_t d = key_digit<KT>((KT)key[it], br.base, shift);
         const uint64_t m = digit_peers(d, valid, nbits);
         const uint32_t before = __popcll(m & lt_mask);
         const bool leader = valid && before == 0;
@@ -478,10 +492,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t i = wbase + it * kWave + lane;
         if (i < br.hi) {
-            const uint32_t d = ((key[it] - br.base) >> shift) & 255u;
+            const uint32_t d = key_digit<KT>((KT)key[it], br.base, shift);
             const uint32_t lp = dbase[d] + wcnt[w][d] + rank[it];
             if (lp < (uint32_t)kSortTile) {   // always true when the counts agree
-                skey[lp] = key[it];
+                skey[lp] = (KT)key[it];
                 sval[lp] = val[it];
             }
         }
@@ -492,14 +506,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int nloc = (int)(br.hi - br.lo);
     const int64_t n_out = segs ? (int64_t)segs[nseg].end : live_count(n_dev, cap, n_host);
     for (int i = threadIdx.x; i < nloc; i += kSortThreads) {
-        const uint32_t k = skey[i];
-        const uint32_t pos = gshift[((k - br.base) >> shift) & 255u] + (uint32_t)i;
+        const KT k = skey[i];
+        const uint32_t pos = gshift[key_digit<KT>(k, br.base, shift)] + (uint32_t)i;
         if (pos < n_out) {   // always true when histogram and scatter agree
             if (kout) kout[pos] = k;
             vout[pos] = sval[i];
-            if (ranges && (int64_t)k < nkeys) {
-                if (i == 0 || skey[i - 1] != k) atomicMin(&ranges[2 * (int64_t)k], pos);
-                if (i == nloc - 1 || skey[i + 1] != k) atomicMax(&ranges[2 * (int64_t)k + 1], pos + 1);
+            // the tile a key names: local keys sit on the segment's base
+            const int64_t gk = kLocal ? (int64_t)br.base + (int64_t)k : (int64_t)k;
+            if (ranges && gk < nkeys) {
+                if (i == 0 || skey[i - 1] != k) atomicMin(&ranges[2 * gk], pos);
+                if (i == nloc - 1 || skey[i + 1] != k) atomicMax(&ranges[2 * gk + 1], pos + 1);
             }
         }
     }
@@ -530,7 +546,8 @@ size_t radix_temp_bytes(int64_t max_items, int32_t max_segs)
            (size_t)(max_segs + 1) * sizeof(SegDesc) + 256;
 }
 
-hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b,
+template <typename KT>
+hipError_t radix_sort_pairs(KT *keys_a, uint32_t *vals_a, KT *keys_b,
                             uint32_t *vals_b, int64_t cap, const unsigned long long *n_dev,
                             int64_t n_host, int bits, void *temp, bool *result_in_b,
                             hipStream_t st, const SortSegments *seg)
@@ -560,11 +577,12 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
     }
     uint32_t *ranges = seg && seg->nkeys > 0 ? seg->ranges : nullptr;
     const int passes = bits <= 8 ? 1 : (bits + 7) / 8;   // one pass at least: ranges come from it
-    uint32_t *ki = keys_a, *vi = vals_a, *ko = keys_b, *vo = vals_b;
+    KT *ki = keys_a, *ko = keys_b;
+    uint32_t *vi = vals_a, *vo = vals_b;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         const int nbits = std::max(1, std::min(8, bits - shift));
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, segs,
+        hipLaunchKernelGGL(k_radix_hist<KT>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki, segs,
                            nseg, n_dev, cap, n_host, shift, hist);
         hipLaunchKernelGGL(k_hist_scan_reduce, dim3((unsigned)nparts), dim3(kSortThreads), 0,
                            st, hist, hlen, parts);
@@ -574,7 +592,7 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
                            hist, hlen, parts, hist);
         // the keys of the last pass are not read again once the ranges are out
         const bool last = p == passes - 1;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
+        hipLaunchKernelGGL(k_radix_scatter<KT>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, ki,
                            vi, last && ranges ? nullptr : ko, vo, hist, segs, nseg, n_dev, cap,
                            n_host, shift, nbits, last ? ranges : nullptr, seg ? seg->nkeys : 0);
         std::swap(ki, ko);
@@ -586,5 +604,12 @@ hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b
                            0, st, ranges, seg->nkeys);
     return hipGetLastError();
 }
+
+template hipError_t radix_sort_pairs<uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, int64_t,
+                                               const unsigned long long *, int64_t, int, void *, bool *,
+                                               hipStream_t, const SortSegments *);
+template hipError_t radix_sort_pairs<uint16_t>(uint16_t *, uint32_t *, uint16_t *, uint32_t *, int64_t,
+                                               const unsigned long long *, int64_t, int, void *, bool *,
+                                               hipStream_t, const SortSegments *);
 
 }  // namespace ss

@@ -171,7 +171,10 @@ struct SortSegments {
 // Stable LSD radix sort of (key, value) uint32 pairs on the low `bits` bits of key
 // (of key minus its segment base with `seg`).  Item count is n_dev ? min(*n_dev, cap) :
 // n_host.  Returns (via *result_in_b) whether the sorted data ended in the b buffers.
-hipError_t radix_sort_pairs(uint32_t *keys_a, uint32_t *vals_a, uint32_t *keys_b,
+// KT = uint16_t sorts keys local to their segment (tile ids within a view, at most
+// 2^16 per view); the tile ranges are then written at the segment's base plus the key.
+template <typename KT>
+hipError_t radix_sort_pairs(KT *keys_a, uint32_t *vals_a, KT *keys_b,
                             uint32_t *vals_b, int64_t cap, const unsigned long long *n_dev,
                             int64_t n_host, int bits, void *temp, bool *result_in_b,
                             hipStream_t st, const SortSegments *seg = nullptr);
@@ -191,10 +194,12 @@ hipError_t launch_project(const float *sorted, int64_t n, int32_t nv, const View
 // holding the inverse of order.
 hipError_t launch_vis_to_rank(const float *vis, int64_t n, int32_t nv, const uint32_t *order,
                               uint32_t *rank, float *out, hipStream_t st);
+// keys16: tile ids local to the view as uint16 (views of at most 2^16 tiles), else the
+// global tile id as uint32; `keys` points at the chosen width.
 hipError_t launch_emit(const uint32_t *order, int64_t n, int32_t nv, const ViewDesc *views,
                        const short4 *tiles, const uint32_t *counts, const uint32_t *offsets,
-                       uint64_t cap, uint32_t *keys, uint32_t *vals, const uint32_t *tmask,
-                       hipStream_t st);
+                       uint64_t cap, void *keys, bool keys16, uint32_t *vals,
+                       const uint32_t *tmask, hipStream_t st);
 hipError_t launch_raster_fwd(int ts, bool depth_only, bool has_vis, int32_t total_tiles,
                              int32_t nv, const ViewDesc *views, const uint32_t *ranges,
                              const uint32_t *lists, const float *rec, int64_t n,

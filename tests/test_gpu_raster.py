@@ -72,6 +72,14 @@ def test_binning_bit_exact_many_sort_blocks_per_view():
     assert min(pairs) > 5 * 4096
 
 
+def test_binning_bit_exact_with_32_bit_tile_keys():
+    """Views of up to 2^16 tiles sort 16-bit tile keys local to the view; a 2080 x 2056
+    view at 8 x 8 has 66,820 tiles, so this plan sorts 32-bit global keys."""
+    sc = scene_tiny(seed=10, views=((2080, 2056), (60, 50)), n=3000, extent=40.0)
+    pairs = check_binning(sc, 8)
+    assert min(pairs) > 0
+
+
 def test_records_centre_matches_fp64():
     sc = scene_tiny(seed=5)
     plan, surf, views = make_plan(sc)
