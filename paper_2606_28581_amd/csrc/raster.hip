@@ -1148,16 +1148,16 @@ __device__ __forceinline__ void pair_gradients(const PairEval &e, bool contrib, 
 //   dL/dalpha_i = T_i (g . f_i) - (g . S_i) / (1 - alpha_i)           (Eq. rasterization)
 // then through alpha = min(alpha_max, o G), G = exp(-rho/2), rho = |Q delta|^2 or
 // |delta|^2 / sigma^2, delta = x - c, z = z0 - k . u.  Each 16-lane row of a wave owns a
-// 4x4 quadrant of the wave's 8x8 pixels and walks, back to front, only the staged records
-// that any of its pixels composited in the forward (8x8 tiles: the forward's contributor
-// masks) or whose box meets the quadrant (other tile sizes: 4 ballots per chunk of 64).
-// A lane takes part in a pair only where the forward composited it - its own mask bit, or
-// the forward's box and alpha tests - so the walk revisits exactly the forward's pairs.
+// 4x4 quadrant of the wave's 8x8 pixels and walks, back to front, the staged records
+// whose box meets the quadrant (4 ballots per chunk of 64).  A lane takes part in a pair
+// only where the forward composited it - the forward's box and FP32 alpha tests and the
+// pixel's `last` - so the walk revisits exactly the forward's pairs.  (8x8 tiles with
+// the forward's contributor masks use the record-parallel kernel below.)
 // The 16 record-gradient values are reduced within the row and added with one atomic per
 // lane, so one instruction carries the sums of up to four records.
 // The colour adjoint of Eq. image_formation runs first per pixel; its 15 per-view
 // sums are reduced per tile into colour_partials.
-template <int TS, bool HAS_VIS, bool DIST, bool CM>
+template <int TS, bool HAS_VIS, bool DIST>
 __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 ? 5 : 4))) void k_raster_bwd(
     int32_t nv, const ViewDesc *__restrict__ views, const uint32_t *__restrict__ ranges,
     const uint32_t *__restrict__ lists, const float4 *__restrict__ rec, int64_t n,
@@ -1166,8 +1166,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     const float *__restrict__ Vin, const float *__restrict__ Tin,
     const int32_t *__restrict__ lastin, const float *__restrict__ dI,
     const float *__restrict__ dD, const float *__restrict__ dN, float *__restrict__ recgrad,
-    float *__restrict__ colour_partials, const unsigned long long *__restrict__ cmask,
-    DistArgs da)
+    float *__restrict__ colour_partials, DistArgs da)
 {
     constexpr int NT = TS * TS;
     constexpr int NW = NT / 64;
@@ -1238,10 +1237,6 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
     }
     // batches on the forward's grid ([k * batch, (k + 1) * batch) from the list start),
     // back to front; the first one is cut at the tile's largest `last`
-    constexpr bool use_cm = CM;              // 8x8 tiles with the forward's contributor masks
-    static_assert(!CM || TS == 8, "contributor masks exist for 8x8 tiles only");
-    const size_t wbase = (size_t)(start >> 6) + (size_t)tile;
-    const int pidx = ((py - wy0) << 3) | (px - wx0);   // the forward's lane of this pixel
     const int nbat = (blk_last + batch - 1) / batch;
     if (nbat > 0) {
         const int bb0 = (nbat - 1) * batch;
@@ -1260,19 +1255,7 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
         if (kb > 0) SS_FETCH_BWD(bb - batch, batch);
         for (int c0 = ((nb - 1) >> 6) << 6; c0 >= 0; c0 -= 64) {
             const int cnt = min(64, nb - c0);
-            uint64_t m = 0, own = 0;
-            if constexpr (use_cm) {
-                // the row walks the records any of its 16 pixels composited in the forward;
-                // a lane takes part only where its own pixel did (its forward mask bit)
-                const int P0 = bb + c0, sh = P0 & 63;
-                const unsigned long long *wp = cmask + (wbase + (P0 >> 6)) * 64 + pidx;
-                if (inside) {
-                    own = wp[0] >> sh;
-                    if (sh != 0 && sh + cnt > 64) own |= wp[64] << (64 - sh);
-                }
-                own &= cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
-                m = row_or64(own);
-            } else {
+            uint64_t m = 0;
             // lane t tests chunk record c0 + t against the wave's four 4x4 quadrants
             uint32_t qbits = 0;
             if (lane < cnt) {
@@ -1290,7 +1273,6 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 const uint64_t bq = __ballot((qbits >> q) & 1u);
                 m = quad == q ? bq : m;
             }
-            }
             const int lim = row_last - (bb + c0);        // chunk records j < lim can contribute
             m &= lim >= 64 ? ~0ull : (lim <= 0 ? 0ull : ((1ull << lim) - 1ull));
             // row-uniform walk, highest position first
@@ -1305,20 +1287,13 @@ __global__ __launch_bounds__(TS *TS) __attribute__((amdgpu_waves_per_eu(TS == 8 
                 // contribute (outside [0, last) or alpha < alpha_min) get zero gradients
                 // and leave T and the suffix unchanged
                 const PairEval e = eval_pair(r0, r1, r2, r3, fx, fy, rc);
-                // the forward's own decision for this pair: its mask bit (8x8 tiles), else
-                // the same FP32 alpha test inside the pixel's FP64 box (the forward never
-                // evaluates a pair outside it)
-                // (a set mask bit also implies the pair lies before the pixel's `last`)
-                bool contrib;
-                if constexpr (use_cm) {
-                    contrib = act && ((own >> jl) & 1ull);
-                } else {
-                    const uint32_t bx = __float_as_uint(r0.x), by = __float_as_uint(r0.y);
-                    const int xlo = (int)(int16_t)(bx & 0xFFFFu), xhi = (int)(int16_t)(bx >> 16);
-                    const int ylo = (int)(int16_t)(by & 0xFFFFu), yhi = (int)(int16_t)(by >> 16);
-                    contrib = act && bb + j < mylast && px >= xlo && px <= xhi && py >= ylo &&
-                              py <= yhi && e.alpha >= rc.alpha_min;
-                }
+                // the forward's own decision for this pair: the same FP32 alpha test inside
+                // the pixel's FP64 box (the forward never evaluates a pair outside it)
+                const uint32_t bx = __float_as_uint(r0.x), by = __float_as_uint(r0.y);
+                const int xlo = (int)(int16_t)(bx & 0xFFFFu), xhi = (int)(int16_t)(bx >> 16);
+                const int ylo = (int)(int16_t)(by & 0xFFFFu), yhi = (int)(int16_t)(by >> 16);
+                const bool contrib = act && bb + j < mylast && px >= xlo && px <= xhi && py >= ylo &&
+                                     py <= yhi && e.alpha >= rc.alpha_min;
                 // a step where no lane of the wave contributes changes nothing (a branch
                 // around the rest, and the loop test at the bottom, keep a single back edge:
                 // no register copies per step)
@@ -1596,9 +1571,9 @@ static void launch_bwd_d(dim3 grid, size_t lds, hipStream_t st, int32_t nv,
             return;
         }
     }
-    hipLaunchKernelGGL((k_raster_bwd<TS, HV, DIST, false>), grid, dim3(TS * TS), lds, st, nv, views,
+    hipLaunchKernelGGL((k_raster_bwd<TS, HV, DIST>), grid, dim3(TS * TS), lds, st, nv, views,
                        ranges, lists, reinterpret_cast<const float4 *>(rec), n, rc, colC, colc, amb,
-                       A, V, T, last, dI, dD, dN, recgrad, cp, cmask, da);
+                       A, V, T, last, dI, dD, dN, recgrad, cp, da);
 }
 
 template <int TS, bool HV>

@@ -170,6 +170,23 @@ def test_backward_multiview_with_colour_and_vis(ts, batch):
     check_backward(sc, plan, surf, views, out, ref, vis=vis)
 
 
+def test_backward_8x8_without_contributor_masks():
+    """A plan laid out for 16x16 tiles and switched to 8x8 has no room for contributor
+    masks: the 8x8 backward then takes the box-test walk, which must give the same
+    gradients."""
+    sc = scene_tiny(seed=14)
+    vis = np.random.default_rng(3).uniform(size=(3, 400)).astype(np.float32)
+    plan, surf, views = make_plan(sc, ts=16, batch=64)
+    # room for the 8x8 pairs in a workspace laid out at 16x16 (no mask words)
+    plan.bind(8 * plan.cap_main, plan.cap_sun)
+    plan.set_settings(ss.default_settings(tile_size=8, batch_depth=64))
+    m, _ = plan.count_pairs(surf, views)
+    assert m <= plan.cap_main
+    out = plan.forward(surf, views, torch.as_tensor(vis, device="cuda"))
+    ref = oracle.forward(sc, oracle_settings(ts=8), vis=vis)
+    check_backward(sc, plan, surf, views, out, ref, vis=vis)
+
+
 def test_backward_config1():
     sc = synth.make_scene(synth.config(1))
     plan, surf, views = make_plan(sc)
