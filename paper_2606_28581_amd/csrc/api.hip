@@ -233,7 +233,7 @@ static Layout make_layout(const ss_plan *p, int64_t cm, int64_t cs)
     // normal-consistency loss: per-pixel depth-adjoint seeds, per-view cameras, block sums
     L.geom_seeds = take((size_t)p->P * 8);
     L.geom_cams = take(nv * sizeof(GeomCam));
-    L.geom_parts = take((size_t)std::max(normal_loss_blocks(max_view_pixels(p)) * 10,
+    L.geom_parts = take((size_t)std::max(normal_loss_blocks(p->vmain.data(), p->nv) * 10,
                                          l1_blocks(max_view_pixels(p))) * nv * 8);
     L.total = o;
     return L;
@@ -846,7 +846,7 @@ ss_status ss_normal_loss(ss_plan *p, const ss_views *v, const float *depth, cons
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const Layout &L = p->L;
     StageScope scope(p, SS_STAGE_NORMAL_LOSS, st);
-    SS_HIP(launch_normal_loss(p->at<ViewDesc>(L.views_main), p->nv, max_view_pixels(p), v->Fxy,
+    SS_HIP(launch_normal_loss(p->at<ViewDesc>(L.views_main), p->vmain.data(), p->nv, max_view_pixels(p), v->Fxy,
                               v->dF, depth, T_final, normal, weight, tau,
                               p->at<GeomCam>(L.geom_cams), p->at<float2>(L.geom_seeds),
                               p->at<double>(L.geom_parts), loss, normal_d, d_depth, d_normal,

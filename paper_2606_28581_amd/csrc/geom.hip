@@ -52,36 +52,34 @@ __device__ __forceinline__ bool covered(const float *T, int64_t g, double tau)
     return 1.0 - (double)T[g] >= tau;
 }
 
-__device__ __forceinline__ double zbar_at(const float *D, const float *T, int64_t g)
+// zbar = D / (1 - T) of pixel g and whether 1 - T >= tau there (zbar is only used where
+// it holds)
+__device__ __forceinline__ double zbar_cov(const float *D, const float *T, int64_t g, double tau,
+                                           bool &cov)
 {
-    return (double)D[g] / (1.0 - (double)T[g]);
+    const double a = 1.0 - (double)T[g];
+    cov = a >= tau;
+    return cov ? (double)D[g] / a : 0.0;
 }
 
-// Pixels of view blockIdx.y, kGeomPx per thread at a stride of the block size: depth
-// normal, loss term, d_normal (added), the z-adjoint seeds s = Minv[:, 2] . dL/dgrad p
-// stored per pixel, and per block the sums of the loss terms and of dL/dMinv (10 doubles),
-// reduced once per thread after its pixels.
-constexpr int kGeomPx = 8;
+// Blocks of kNlCols x kNlRows pixels of view blockIdx.y, one column per thread, walked
+// row by row: each thread keeps zbar of rows y - 1, y, y + 1 of its column in registers
+// and the block shares row y (with one halo column on each side) through LDS, so every
+// pixel's zbar is computed once (plus two halo rows per block).  Per pixel: depth normal,
+// loss term, d_normal (added), the z-adjoint seeds s = Minv[:, 2] . dL/dgrad p stored per
+// pixel, and per block the sums of the loss terms and of dL/dMinv (10 doubles).
+constexpr int kNlCols = 256;
+constexpr int kNlRows = 16;
 
 __device__ __forceinline__ void normal_loss_pixel(
-    const ViewDesc &vd, int64_t local, const GeomCam &c, const float *__restrict__ D,
-    const float *__restrict__ T, const float *__restrict__ Nr, double wv, double tau,
-    float *__restrict__ Nd_out, float *__restrict__ d_normal, float2 *__restrict__ seeds,
-    double (&acc)[10])
+    int64_t P, int64_t g, int64_t b3, bool valid, double dzx, double dzy, const GeomCam &c,
+    const float (&nr)[3], const float (&dn)[3], double wv, float *__restrict__ Nd_out,
+    float *__restrict__ d_normal, float2 *__restrict__ seeds, double (&acc)[10])
 {
-    const int64_t P = (int64_t)vd.W * vd.H;
-    const int i = (int)(local % vd.W), j = (int)(local / vd.W);
-    const int64_t g = vd.pix_off + local;
-    const int64_t b3 = 3 * vd.pix_off + local;
-    bool valid = i > 0 && j > 0 && i < vd.W - 1 && j < vd.H - 1;
-    valid = valid && covered(T, g, tau) && covered(T, g - 1, tau) && covered(T, g + 1, tau) &&
-            covered(T, g - vd.W, tau) && covered(T, g + vd.W, tau);
     float2 s = make_float2(0.f, 0.f);
     float nd[3] = {0.f, 0.f, 0.f};
     if (valid) {
         const double *Mi = c.Minv;
-        const double dzx = zbar_at(D, T, g + 1) - zbar_at(D, T, g - 1);
-        const double dzy = zbar_at(D, T, g + vd.W) - zbar_at(D, T, g - vd.W);
         double gx[3], gy[3], n[3];
         for (int r = 0; r < 3; ++r) {
             gx[r] = 2.0 * Mi[3 * r] + dzx * Mi[3 * r + 2];
@@ -95,11 +93,11 @@ __device__ __forceinline__ void normal_loss_pixel(
         double N[3], R[3];
         for (int r = 0; r < 3; ++r) {
             N[r] = sgn * n[r] * inn;
-            R[r] = (double)Nr[b3 + r * P];
+            R[r] = (double)nr[r];
         }
         acc[9] += 1.0 - (R[0] * N[0] + R[1] * N[1] + R[2] * N[2]);
         for (int r = 0; r < 3; ++r) {
-            d_normal[b3 + r * P] += (float)(-wv * N[r]);
+            d_normal[b3 + r * P] = dn[r] + (float)(-wv * N[r]);
             nd[r] = (float)N[r];
         }
         // dL/dN = -wv N_r -> dL/dn = sgn (gN - N (N . gN)) / |n|
@@ -127,13 +125,15 @@ __device__ __forceinline__ void normal_loss_pixel(
     }
 }
 
-__global__ __launch_bounds__(kGeomThreads) void k_normal_loss(
+__global__ __launch_bounds__(kNlCols) void k_normal_loss(
     const ViewDesc *__restrict__ views, const GeomCam *__restrict__ cams,
     const float *__restrict__ D, const float *__restrict__ T, const float *__restrict__ Nr,
     double weight, double tau, float *__restrict__ Nd_out, float *__restrict__ d_normal,
     float2 *__restrict__ seeds, double *__restrict__ partials, int blocks_per_view)
 {
-    __shared__ double red[kGeomThreads / 64][10];
+    __shared__ double zrow[2][kNlCols + 2];
+    __shared__ int crow[2][kNlCols + 2];
+    __shared__ double red[kNlCols / 64][10];
     const int v = blockIdx.y;
     const ViewDesc vd = views[v];
     const int64_t P = (int64_t)vd.W * vd.H;
@@ -142,10 +142,82 @@ __global__ __launch_bounds__(kGeomThreads) void k_normal_loss(
     double acc[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.0;
-    const int64_t l0 = (int64_t)blockIdx.x * (kGeomThreads * kGeomPx) + threadIdx.x;
-    for (int r = 0; r < kGeomPx; ++r) {
-        const int64_t local = l0 + (int64_t)r * kGeomThreads;
-        if (local < P) normal_loss_pixel(vd, local, c, D, T, Nr, wv, tau, Nd_out, d_normal, seeds, acc);
+    const int nbx = (vd.W + kNlCols - 1) / kNlCols, nby = (vd.H + kNlRows - 1) / kNlRows;
+    if ((int)blockIdx.x < nbx * nby) {   // uniform over the block
+        const int tid = threadIdx.x;
+        const int x0 = ((int)blockIdx.x % nbx) * kNlCols, y0 = ((int)blockIdx.x / nbx) * kNlRows;
+        const int y1 = min(y0 + kNlRows, vd.H);
+        const int x = x0 + tid;
+        const bool incol = x < vd.W;
+        // threads 0 and 1 also fill the halo columns x0 - 1 and x0 + kNlCols
+        const int hx = tid == 0 ? x0 - 1 : x0 + kNlCols;
+        const bool halo = tid < 2 && hx >= 0 && hx < vd.W;
+        const int hslot = tid == 0 ? 0 : kNlCols + 1;
+        const int64_t base = vd.pix_off;
+        const double one = 1.0;
+        auto zbar = [&](float d, float t, bool &cov) {
+            const double a = one - (double)t;
+            cov = a >= tau;
+            return cov ? (double)d / a : 0.0;
+        };
+        bool cm = false, cc = false;   // 1 - T >= tau at (x, y - 1), (x, y)
+        double zm = 0.0, zc = 0.0;
+        if (incol && y0 > 0) zm = zbar_cov(D, T, base + (int64_t)(y0 - 1) * vd.W + x, tau, cm);
+        if (incol) zc = zbar_cov(D, T, base + (int64_t)y0 * vd.W + x, tau, cc);
+        // D and T of the next row (of the column, and of the halo column) are loaded one
+        // row ahead, so no row waits for its own loads behind the barrier
+        float Dn = 0.f, Tn = 1.f, Dh = 0.f, Th = 1.f;
+        if (incol && y0 + 1 < vd.H) {
+            Dn = D[base + (int64_t)(y0 + 1) * vd.W + x];
+            Tn = T[base + (int64_t)(y0 + 1) * vd.W + x];
+        }
+        if (halo) {
+            Dh = D[base + (int64_t)y0 * vd.W + hx];
+            Th = T[base + (int64_t)y0 * vd.W + hx];
+        }
+        for (int y = y0; y < y1; ++y) {
+            bool cp = false;
+            double zp = 0.0;
+            if (incol && y + 1 < vd.H) zp = zbar(Dn, Tn, cp);
+            const int64_t local = (int64_t)y * vd.W + x;
+            float nr[3] = {0.f, 0.f, 0.f}, dn[3] = {0.f, 0.f, 0.f};
+            if (incol) {
+                for (int r = 0; r < 3; ++r) {
+                    nr[r] = Nr[3 * base + local + r * P];
+                    dn[r] = d_normal[3 * base + local + r * P];
+                }
+            }
+            const int buf = y & 1;
+            zrow[buf][tid + 1] = zc;
+            crow[buf][tid + 1] = incol && cc;
+            if (tid < 2) {
+                bool ch = false;
+                const double zh = halo ? zbar(Dh, Th, ch) : 0.0;
+                zrow[buf][hslot] = zh;
+                crow[buf][hslot] = ch;
+            }
+            if (incol && y + 2 < vd.H) {
+                Dn = D[base + (int64_t)(y + 2) * vd.W + x];
+                Tn = T[base + (int64_t)(y + 2) * vd.W + x];
+            }
+            if (halo && y + 1 < vd.H) {
+                Dh = D[base + (int64_t)(y + 1) * vd.W + hx];
+                Th = T[base + (int64_t)(y + 1) * vd.W + hx];
+            }
+            // one barrier per row: row y + 1 goes to the other buffer, whose readers (row
+            // y - 1) have all passed this barrier
+            __syncthreads();
+            if (incol) {
+                const bool valid = x > 0 && y > 0 && x < vd.W - 1 && y < vd.H - 1 && cc && cm && cp &&
+                                   crow[buf][tid] && crow[buf][tid + 2];
+                const double dzx = zrow[buf][tid + 2] - zrow[buf][tid];
+                const double dzy = zp - zm;
+                normal_loss_pixel(P, base + local, 3 * base + local, valid, dzx, dzy, c, nr, dn, wv,
+                                  Nd_out, d_normal, seeds, acc);
+            }
+            zm = zc; cm = cc;
+            zc = zp; cc = cp;
+        }
     }
     // block sums: wave shuffles, then the waves' sums through LDS
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -158,7 +230,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_normal_loss(
     __syncthreads();
     if (threadIdx.x < 10) {
         double x = 0.0;
-        for (int w = 0; w < kGeomThreads / 64; ++w) x += red[w][threadIdx.x];
+        for (int w = 0; w < kNlCols / 64; ++w) x += red[w][threadIdx.x];
         partials[((size_t)v * blocks_per_view + blockIdx.x) * 10 + threadIdx.x] = x;
     }
 }
@@ -217,23 +289,30 @@ __global__ void k_normal_loss_reduce(const ViewDesc *__restrict__ views,
         }
 }
 
-int normal_loss_blocks(int64_t max_view_pixels)
+int normal_loss_blocks(const ViewDesc *host_views, int32_t nv)
 {
-    return (int)((max_view_pixels + kGeomThreads * kGeomPx - 1) / (kGeomThreads * kGeomPx));
+    int64_t m = 0;
+    for (int32_t v = 0; v < nv; ++v) {
+        const int64_t nbx = ((int64_t)host_views[v].W + kNlCols - 1) / kNlCols;
+        const int64_t nby = ((int64_t)host_views[v].H + kNlRows - 1) / kNlRows;
+        m = std::max(m, nbx * nby);
+    }
+    return (int)m;
 }
 
-hipError_t launch_normal_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pixels,
+hipError_t launch_normal_loss(const ViewDesc *views, const ViewDesc *host_views, int32_t nv,
+                              int64_t max_view_pixels,
                               const float *Fxy, const float *dF, const float *D, const float *T,
                               const float *Nr, float weight, float tau, GeomCam *cams,
                               float2 *seeds, double *partials, float *loss, float *Nd_out,
                               float *d_depth, float *d_normal, float *d_dF, hipStream_t st)
 {
     if (nv <= 0) return hipSuccess;
-    const int bpv = normal_loss_blocks(max_view_pixels);
+    const int bpv = normal_loss_blocks(host_views, nv);
     hipLaunchKernelGGL(k_geom_cameras, dim3((unsigned)((nv + 63) / 64)), dim3(64), 0, st, Fxy, dF, nv,
                        cams);
     if (bpv > 0) {
-        hipLaunchKernelGGL(k_normal_loss, dim3((unsigned)bpv, (unsigned)nv), dim3(kGeomThreads), 0, st,
+        hipLaunchKernelGGL(k_normal_loss, dim3((unsigned)bpv, (unsigned)nv), dim3(kNlCols), 0, st,
                            views, cams, D, T, Nr, (double)weight, (double)tau, Nd_out, d_normal,
                            seeds, partials, bpv);
         const int dbl = (int)((max_view_pixels + kGeomThreads - 1) / kGeomThreads);

@@ -646,15 +646,18 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
     // LDS stride between a record's float4 groups: a compile-time constant (>= every
     // batch) so that the group reads are immediate offsets from one address
     constexpr int BS = NT < 256 ? NT : 256;
+    // records of the next batch in q0..q5, list entries of the one after in nidx: the
+    // gather never waits for the list load it depends on
     float4 q0, q1, q2, q3, q4, q5;
-#define SS_FETCH_FWD(BASE, CNT)                                                        \
-    if (tid < (CNT)) {                                                                 \
-        const uint32_t idx_ = min(lists[(BASE) + tid], (uint32_t)(n - 1));             \
-        const float4 *src_ = recv + (size_t)idx_ * RS;                           \
+    uint32_t nidx = 0;
+#define SS_FETCH_FWD(IDX)                                                              \
+    {                                                                                  \
+        const float4 *src_ = recv + (size_t)min((IDX), (uint32_t)(n - 1)) * RS;       \
         q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3];                        \
         if (!DEPTH_ONLY) { q4 = src_[4]; q5 = src_[5]; }                               \
     }
-    if (start < end) { SS_FETCH_FWD(start, (int)min((uint32_t)B, end - start)); }
+    if (start < end && tid < (int)min((uint32_t)B, end - start)) SS_FETCH_FWD(lists[start + tid]);
+    if (start + B < end && tid < (int)min((uint32_t)B, end - start - B)) nidx = lists[start + B + tid];
     const size_t wbase = (size_t)(start >> 6) + (size_t)tile;   // tiles' word ranges are disjoint
     unsigned long long wacc = 0ull;
     int wcur = -1;
@@ -666,8 +669,9 @@ __global__ __launch_bounds__(TS *TS) void k_raster_fwd(
             if (!DEPTH_ONLY) { lds[4 * BS + tid] = q4; lds[5 * BS + tid] = q5; }
         }
         __syncthreads();
-        const uint32_t b1 = b0 + B;
-        if (b1 < end) { SS_FETCH_FWD(b1, (int)min((uint32_t)B, end - b1)); }
+        const uint32_t b1 = b0 + B, b2 = b1 + B;
+        if (b1 < end && tid < (int)min((uint32_t)B, end - b1)) SS_FETCH_FWD(nidx);
+        if (b2 < end && tid < (int)min((uint32_t)B, end - b2)) nidx = lists[b2 + tid];
         const int pos0 = (int)(b0 - start);
         for (int c0 = 0; c0 < nb; c0 += 64) {
             if (__ballot(!done) == 0) break;
@@ -1440,19 +1444,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int blk_last = min(max_last, tile_len);
     const size_t wbase = (size_t)(start >> 6) + (size_t)tile;
     const int pidx = ((opy - wy0) << 3) | (opx - wx0);
+    // records of the next batch in q0..q5, list entries of the one after in nidx
     float4 q0, q1, q2, q3, q4, q5;
-    uint32_t qidx = 0;
-#define SS_FETCH_RP(BB, CNT)                                                           \
-    if (lane < (CNT)) {                                                                \
-        qidx = min(lists[start + (BB) + lane], (uint32_t)(n - 1));                     \
+    uint32_t qidx = 0, nidx = 0;
+#define SS_FETCH_RP(IDX)                                                               \
+    {                                                                                  \
+        qidx = min((IDX), (uint32_t)(n - 1));                                          \
         const float4 *src_ = recv + (size_t)qidx * kRecStride4;                        \
         q0 = src_[0]; q1 = src_[1]; q2 = src_[2]; q3 = src_[3]; q4 = src_[4]; q5 = src_[5]; \
     }
     const int nbat = (blk_last + batch - 1) / batch;
     if (nbat > 0) {
         const int bb0 = (nbat - 1) * batch;
-        SS_FETCH_RP(bb0, blk_last - bb0);
+        if (lane < blk_last - bb0) SS_FETCH_RP(lists[start + bb0 + lane]);
     }
+    if (nbat > 1 && lane < batch) nidx = lists[start + (nbat - 2) * batch + lane];
     for (int kb = nbat - 1; kb >= 0; --kb) {
         const int bb = kb * batch;
         const int nb = min(bb + batch, blk_last) - bb;
@@ -1476,7 +1482,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         ownw[lane] = own;
         const uint64_t un = row_or64(own);          // row q: the union of quadrant q
         __syncthreads();
-        if (kb > 0) SS_FETCH_RP(bb - batch, batch);
+        if (kb > 0 && lane < batch) SS_FETCH_RP(nidx);
+        if (kb > 1 && lane < batch) nidx = lists[start + bb - 2 * batch + lane];
         for (int q = 0; q < 4; ++q) {
             const uint64_t U = ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(un >> 32), 16 * q) << 32) |
                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)un, 16 * q);

@@ -243,10 +243,11 @@ hipError_t launch_map_through(const uint32_t *order, int64_t n_order,
                               uint32_t *out, hipStream_t st);
 
 // geom.hip: depth-gradient normals and the normal-consistency loss over all views.
-// seeds: one float2 per pixel; partials: normal_loss_blocks(max view pixels) * nv * 10
-// doubles; cams: nv entries.  loss [nv] is written; d_depth, d_normal and d_dF are added to.
-int normal_loss_blocks(int64_t max_view_pixels);
-hipError_t launch_normal_loss(const ViewDesc *views, int32_t nv, int64_t max_view_pixels,
+// seeds: one float2 per pixel; partials: normal_loss_blocks(host views) * nv * 10 doubles;
+// cams: nv entries.  loss [nv] is written; d_depth, d_normal and d_dF are added to.
+int normal_loss_blocks(const ViewDesc *host_views, int32_t nv);
+hipError_t launch_normal_loss(const ViewDesc *views, const ViewDesc *host_views, int32_t nv,
+                              int64_t max_view_pixels,
                               const float *Fxy, const float *dF, const float *D, const float *T,
                               const float *Nr, float weight, float tau, GeomCam *cams,
                               float2 *seeds, double *partials, float *loss, float *Nd_out,

@@ -71,8 +71,12 @@ def test_distortion_forward_and_backward_match_oracle(ts, batch):
         assert rel_err(to_np(g2[k]), gr2[k]) < 1e-3, k
 
 
-def test_normal_loss_kernel_matches_oracle_on_the_same_maps():
-    sc = scene(seed=11)
+# the kernel walks blocks of 256 columns x 16 rows: the larger views span two blocks
+# across (ragged second, halo columns at the seam) and end in ragged row bands
+@pytest.mark.parametrize("n,views", [(400, ((45, 38), (33, 29), (40, 41))),
+                                     (3000, ((300, 290), (270, 263)))])
+def test_normal_loss_kernel_matches_oracle_on_the_same_maps(n, views):
+    sc = scene(seed=11, n=n, views=views)
     plan, surf, views = make_plan(sc, ts=8)
     out = plan.forward(surf, views)
     maps = {k: to_np(out[k]).astype(np.float64) for k in ("depth", "T", "normal")}
