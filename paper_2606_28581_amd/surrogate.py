@@ -72,6 +72,35 @@ class Mlp:
         return d_w
 
 
+def save_network(path, centre, inv_half, w, m=None, v=None, step=0):
+    """Surrogate checkpoint as an .npz of plain arrays: the normalisation constants the
+    network was trained with (Mlp(ctx, centre, inv_half)), its N_PARAMS weights and, to
+    resume training, the Adam moments and the step count."""
+    host = lambda t: (t.detach().cpu().numpy() if isinstance(t, torch.Tensor) else np.asarray(t)) \
+        .astype(np.float32).reshape(-1)
+    d = dict(centre=np.asarray(centre, np.float64).reshape(3), inv_half=np.float64(inv_half),
+             w=host(w), step=np.int64(step))
+    if (m is None) != (v is None):
+        raise ValueError("give both Adam moments or neither")
+    if m is not None:
+        d["m"], d["v"] = host(m), host(v)
+    for k in ("w", "m", "v"):
+        if k in d and d[k].size != N_PARAMS:
+            raise ValueError(f"{k} holds {d[k].size} values, the network has {N_PARAMS}")
+    np.savez(path, **d)
+
+
+def load_network(path, device="cuda") -> dict:
+    """A save_network file: centre (3 floats), inv_half, step, and w, m, v as float32
+    tensors on `device` (m and v None when the file holds no moments)."""
+    with np.load(path, allow_pickle=False) as z:
+        if z["w"].size != N_PARAMS:
+            raise ValueError(f"checkpoint holds {z['w'].size} weights, the network has {N_PARAMS}")
+        t = lambda k: torch.as_tensor(z[k].astype(np.float32), device=device) if k in z.files else None
+        return dict(centre=z["centre"].astype(np.float64), inv_half=float(z["inv_half"]),
+                    step=int(z["step"]), w=t("w"), m=t("m"), v=t("v"))
+
+
 def adam(w, m, v, g, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
     call("ss_mlp_adam", _ptr(w), _ptr(m), _ptr(v), _ptr(g), w.numel(), float(lr), float(beta1),
          float(beta2), float(eps), int(step), _stream())

@@ -120,6 +120,58 @@ class Trainer:
         # grow the workspace when needed; off for timing loops that check once at the end
         self.check = True
 
+    # ------------------------------------------------------------------ checkpoints
+    _VIEW_TERMS = ("dF", "colC", "colc")
+
+    def state_dict(self) -> dict:
+        """What a resumed run needs, as host arrays: the raw surfel parameters and their
+        Adam moments, the views' learnable terms (camera deltas, colour gain and bias) with
+        their moments, and the step count (Adam's bias correction and the camera start
+        step count from it)."""
+        host = lambda t: t.detach().cpu().numpy().copy()
+        d = {"step_count": np.int64(self.step_count), "raw": host(self.raw), "m": host(self.m),
+             "v": host(self.v)}
+        for k in self._VIEW_TERMS:
+            t = self.views.__dict__[k]
+            if t is not None:
+                d["view_" + k] = host(t)
+        for k, t in self.vstate.items():
+            d["vstate_" + k] = host(t)
+        return d
+
+    def load_state_dict(self, d: dict):
+        """Restores a state_dict of a trainer over the same surfel and view counts (and
+        the same learnable view terms) in place, then rewrites the activated surfel
+        arrays from the raw parameters."""
+        def put(dst: torch.Tensor, a, name):
+            a = np.asarray(a)
+            if tuple(a.shape) != tuple(dst.shape) or a.dtype != np.float32:
+                raise ValueError(f"checkpoint entry {name}: {a.dtype}{tuple(a.shape)} does not fit "
+                                 f"float32{tuple(dst.shape)}")
+            dst.copy_(torch.from_numpy(a))
+        put(self.raw, d["raw"], "raw")
+        put(self.m, d["m"], "m")
+        put(self.v, d["v"], "v")
+        for k in self._VIEW_TERMS:
+            t = self.views.__dict__[k]
+            if (t is None) != ("view_" + k not in d):
+                raise ValueError(f"checkpoint and trainer disagree on the view term {k}")
+            if t is not None:
+                put(t, d["view_" + k], "view_" + k)
+        for k, t in self.vstate.items():
+            put(t, d["vstate_" + k], "vstate_" + k)
+        self.step_count = int(d["step_count"])
+        surfel_activate(self.raw, self.surf)
+        self.out = None
+
+    def save(self, path):
+        """state_dict() into an .npz file (plain arrays, no pickled objects)."""
+        np.savez(path, **self.state_dict())
+
+    def load(self, path):
+        with np.load(path, allow_pickle=False) as z:
+            self.load_state_dict({k: z[k] for k in z.files})
+
     def step(self):
         """One training step; returns (per-view L1 loss, per-view normal loss) tensors (the
         L1 buffer is the trainer's own and is overwritten by the next step)."""

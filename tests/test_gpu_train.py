@@ -174,3 +174,59 @@ def test_training_step_matches_oracle_and_descends():
                           cfg=tr.adam_config(lr_mean=0.001, camera_start=1000, eps=1e-8), weights=w)
     losses = [float(trainer2.step()[0].sum()) for _ in range(12)]
     assert losses[-1] < 0.8 * losses[0], losses
+
+
+def test_trainer_checkpoint_resumes_the_run(tmp_path):
+    """Save after 3 steps, run 3 more; a new trainer over fresh tensors loads the file and
+    runs the same 3 steps.  The restored state is bit-identical (the activated surfels are
+    rewritten from the raw parameters), and the continued run matches up to the gradient
+    atomics' summation order.  The camera group starts at step 2, so the resumed steps
+    depend on the restored step count."""
+    sc = synth.make_scene(synth.tiny(n_surfels=500, views=((36, 31), (30, 34)), seed=24))
+    ds = float(np.float32(2.0 / sc["spec"].extent))
+    w = tr.LossWeights()
+    cfg = tr.adam_config(lr_mean=0.001, camera_start=2, eps=1e-8)
+    keys = ("mean", "t_u", "t_v", "scale", "opacity", "albedo")
+
+    def fresh():
+        plan, surf, views = make_plan(sc, ts=8)
+        return plan, surf, views
+
+    plan, surf, views = fresh()
+    dark = ss.SurfelTensors(surf.mean, surf.t_u, surf.t_v, surf.scale, surf.opacity,
+                            (surf.albedo * 0.7).contiguous())
+    target = plan.forward(dark, views)["image"].clone()
+    A = tr.Trainer(plan, surf, views, target, ds, cfg=cfg, weights=w)
+    for _ in range(3):
+        A.step()
+    path = tmp_path / "trainer.npz"
+    A.save(path)
+    saved = A.state_dict()
+    act = {k: to_np(getattr(surf, k)).copy() for k in keys}
+    la = [float(A.step()[0].sum()) for _ in range(3)]
+    endA = A.state_dict()
+
+    plan_b, surf_b, views_b = fresh()
+    B = tr.Trainer(plan_b, surf_b, views_b, target, ds, cfg=cfg, weights=w)
+    B.load(path)
+    assert B.step_count == 3
+    for k, a in B.state_dict().items():
+        np.testing.assert_array_equal(a, saved[k], err_msg=k)
+    for k in keys:
+        np.testing.assert_array_equal(to_np(getattr(surf_b, k)), act[k], err_msg=k)
+    lb = [float(B.step()[0].sum()) for _ in range(3)]
+    np.testing.assert_allclose(lb, la, rtol=1e-4)
+    endB = B.state_dict()
+    assert endB["step_count"] == endA["step_count"] == 6
+    # in norm: a parameter whose gradient is cancellation noise can take a different
+    # (tiny) Adam step in the two runs
+    for k in endA:
+        if k != "step_count":
+            a, b = endB[k].astype(np.float64), endA[k].astype(np.float64)
+            assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b), k
+    # a checkpoint of another trainer shape is refused
+    sc2 = synth.make_scene(synth.tiny(n_surfels=300, views=((36, 31), (30, 34)), seed=24))
+    plan_c, surf_c, views_c = make_plan(sc2, ts=8)
+    C_ = tr.Trainer(plan_c, surf_c, views_c, target, ds, cfg=cfg, weights=w)
+    with pytest.raises(ValueError):
+        C_.load(path)
