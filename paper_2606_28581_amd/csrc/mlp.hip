@@ -185,7 +185,14 @@ __device__ __forceinline__ void layer_t(const u16 *W, int ldw, const float *bias
     }
 }
 
-// ReLU + bf16 of a layer's accumulators into the next layer's B operands
+// ReLU + bf16 of a layer's accumulators into the next layer's B operands.  The ReLU is
+// one integer max on the bit pattern (every negative float, -0 included, is a negative
+// int32 and becomes +0): a float max would add a NaN-quieting max per value.
+__device__ __forceinline__ float relu(float x)
+{
+    return __int_as_float(max(__float_as_int(x), 0));
+}
+
 __device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][2], Frag (&h)[2][2])
 {
 #pragma unroll
@@ -193,7 +200,7 @@ __device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][2], Frag (
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) h[pt][ks].h[e] = f2bf(fmaxf(acc[2 * ks + (e >> 2)][pt][e & 3], 0.f));
+            for (int e = 0; e < 8; ++e) h[pt][ks].h[e] = f2bf(relu(acc[2 * ks + (e >> 2)][pt][e & 3]));
 }
 
 // the activations of one layer for the backward, [M][64] in neuron order: 4 consecutive
