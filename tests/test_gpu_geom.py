@@ -72,9 +72,11 @@ def test_distortion_forward_and_backward_match_oracle(ts, batch):
 
 
 # the kernel walks blocks of 256 columns x 16 rows: the larger views span two blocks
-# across (ragged second, halo columns at the seam) and end in ragged row bands
+# across (ragged second, halo columns at the seam) and end in ragged row bands; views of
+# 1 x 5 and 3 x 3 pixels have no interior pixel or one
 @pytest.mark.parametrize("n,views", [(400, ((45, 38), (33, 29), (40, 41))),
-                                     (3000, ((300, 290), (270, 263)))])
+                                     (3000, ((300, 290), (270, 263))),
+                                     (400, ((1, 5), (3, 3), (40, 41)))])
 def test_normal_loss_kernel_matches_oracle_on_the_same_maps(n, views):
     sc = scene(seed=11, n=n, views=views)
     plan, surf, views = make_plan(sc, ts=8)
