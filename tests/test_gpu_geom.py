@@ -29,7 +29,7 @@ def cuda(a):
     return torch.as_tensor(np.ascontiguousarray(a, np.float32), device="cuda")
 
 
-@pytest.mark.parametrize("ts,batch", [(8, 64), (16, 64), (8, 48)])
+@pytest.mark.parametrize("ts,batch", [(8, 64), (16, 64), (8, 48), (32, 100)])
 def test_distortion_forward_and_backward_match_oracle(ts, batch):
     sc = scene()
     ds = depth_scale(sc)
