@@ -58,6 +58,7 @@ def loss(plan, surf, views, vis, up, ds):
 
 @pytest.mark.parametrize("ts,mode,with_dist,groups", [(8, 1, True, SURF + VIEW),
                                                       (16, 1, False, SURF + VIEW),
+                                                      (32, 1, True, SURF + VIEW),
                                                       (8, 0, False, KINK_FREE)])
 def test_directional_derivatives_match_central_differences(ts, mode, with_dist, groups):
     sc = synth.make_scene(synth.tiny(n_surfels=80, views=((26, 21), (19, 24)), seed=31))
