@@ -7,13 +7,13 @@
 // with v_mfma_f32_16x16x32_bf16.  Parameters are one FP32 master vector
 // [W1 (64x128), b1, W2 (64x64), b2, W3 (64x64), b3, w4 (64), b4].
 //
-// Forward: one wave owns 32 points (two 16-row MFMA tiles).  Each lane computes exactly
-// the 8 features its A operand needs (point l%16, features 32 ks + 8 (l/16) .. +7), so
-// the 96 sin/cos values of a point are spread over 4 lanes with no duplication and no
-// LDS staging.  Hidden activations go through a small per-wave LDS tile to move from the
-// accumulator layout (4 points x 1 neuron per lane) to the operand layout (1 point x 8
-// neurons per lane).  Weights live in LDS, row-major [out][in], so a B operand is 16
-// contiguous bytes.
+// Forward: one wave step owns 64 points (four 16-point MFMA tiles, so that every weight
+// fragment read from LDS feeds four independent accumulation chains).  Each lane computes
+// exactly the 8 features its operand needs (point l%16, features 32 ks + 8 (l/16) .. +7),
+// so the 96 sin/cos values of a point are spread over 4 lanes with no duplication and no
+// LDS staging; the layers are computed transposed so that hidden activations stay in
+// registers (see k_mlp_forward).  Weights live in LDS, row-major [out][in], so a weight
+// operand is 16 contiguous bytes.  The backward kernels work on 32-point tiles.
 #include "ss_internal.h"
 #include "ss_mlp.h"
 
@@ -24,9 +24,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16;
 
 constexpr int kPtsPerWave = 32;
+// the forward takes kFwdPT tiles of 16 points per wave step: each weight fragment read
+// from LDS feeds kFwdPT independent MFMA chains
+constexpr int kFwdPT = 4;
+constexpr int kFwdPts = 16 * kFwdPT;
 constexpr int kMlpThreads = 256;
 constexpr int kMlpWaves = kMlpThreads / 64;
-constexpr int kHStride = 72;        // bf16 row stride of the per-wave activation tile
 
 // FP32 -> BF16, round to nearest even (gfx950 converts in hardware, two values per
 // instruction when the compiler pairs them)
@@ -164,23 +167,23 @@ __device__ __forceinline__ void layer_mfma(const Frag (&a)[2][KSTEPS], const u16
 
 // One layer, transposed: acc[ot][pt] (neurons 16 ot.., points 16 pt..) = bias +
 // W[ot rows] x[pt] over KSTEPS k-steps; W row-major [out][in] (in LDS).
-template <int KSTEPS>
+template <int KSTEPS, int PT>
 __device__ __forceinline__ void layer_t(const u16 *W, int ldw, const float *bias,
-                                        const Frag (&x)[2][KSTEPS], int lane, f32x4 (&acc)[4][2])
+                                        const Frag (&x)[PT][KSTEPS], int lane, f32x4 (&acc)[4][PT])
 {
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
         const float *bo = bias + ot * 16 + 4 * (lane >> 4);
         const f32x4 b0 = f32x4{bo[0], bo[1], bo[2], bo[3]};
-        acc[ot][0] = b0;
-        acc[ot][1] = b0;
+#pragma unroll
+        for (int pt = 0; pt < PT; ++pt) acc[ot][pt] = b0;
 #pragma unroll
         for (int ks = 0; ks < KSTEPS; ++ks) {
             Frag w;
             w.q = *reinterpret_cast<const uint4 *>(W + (ot * 16 + (lane & 15)) * ldw + ks * 32 +
                                                    8 * (lane >> 4));
 #pragma unroll
-            for (int pt = 0; pt < 2; ++pt) acc[ot][pt] = mfma(w, x[pt][ks], acc[ot][pt]);
+            for (int pt = 0; pt < PT; ++pt) acc[ot][pt] = mfma(w, x[pt][ks], acc[ot][pt]);
         }
     }
 }
@@ -193,10 +196,11 @@ __device__ __forceinline__ float relu(float x)
     return __int_as_float(max(__float_as_int(x), 0));
 }
 
-__device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][2], Frag (&h)[2][2])
+template <int PT>
+__device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][PT], Frag (&h)[PT][2])
 {
 #pragma unroll
-    for (int pt = 0; pt < 2; ++pt)
+    for (int pt = 0; pt < PT; ++pt)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
@@ -205,11 +209,12 @@ __device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][2], Frag (
 
 // the activations of one layer for the backward, [M][64] in neuron order: 4 consecutive
 // neurons (8 bytes) per lane and accumulator tile
-__device__ __forceinline__ void save_layer(const Frag (&h)[2][2], u16 *dst, int64_t base, int64_t M,
+template <int PT>
+__device__ __forceinline__ void save_layer(const Frag (&h)[PT][2], u16 *dst, int64_t base, int64_t M,
                                            int lane)
 {
 #pragma unroll
-    for (int pt = 0; pt < 2; ++pt) {
+    for (int pt = 0; pt < PT; ++pt) {
         const int64_t i = base + pt * 16 + (lane & 15);
         if (i >= M) continue;
 #pragma unroll
@@ -238,19 +243,20 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t ntile = (M + kPtsPerWave - 1) / kPtsPerWave;
+    constexpr int PT = kFwdPT;
+    const int64_t ntile = (M + kFwdPts - 1) / kFwdPts;
     for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
          tile += (int64_t)gridDim.x * kMlpWaves) {
         // weight fragments are read from LDS per tile (held across tiles they would take
         // 128 VGPRs)
         asm volatile("" ::: "memory");
-        const int64_t base = tile * kPtsPerWave;
+        const int64_t base = tile * kFwdPts;
         // all-pairs mode: one division per tile; lanes carry into the next sun
         const int64_t is0 = G > 0 ? base / G : 0, ip0 = base - is0 * G;
         // ---- features in the B layout
-        Frag fa[2][4];
+        Frag fa[PT][4];
 #pragma unroll
-        for (int pt = 0; pt < 2; ++pt) {
+        for (int pt = 0; pt < PT; ++pt) {
             int64_t i = base + pt * 16 + (lane & 15);
             const bool valid = i < M;
             if (!valid) i = M - 1;
@@ -277,8 +283,8 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
                         fa[pt][ks].q;
             }
         }
-        f32x4 acc[4][2];
-        Frag h[2][2];
+        f32x4 acc[4][PT];
+        Frag h[PT][2];
         layer_t<4>(L.W1, kMlpIn, L.b, fa, lane, acc);
         relu_to_operand(acc, h);
         if (saveH) save_layer(h, saveH, base, M, lane);
@@ -290,9 +296,9 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
         if (saveH) save_layer(h, saveH + 2 * M * kMlpWidth, base, M, lane);
         // ---- output: logit = w4 . h3 + b4 (FP32); lane (q, n) holds neurons
         // 16 ot + 4 q + 0..3 of point n, so the 4 lane groups of a column are summed
-        float part[2];
+        float part[PT];
 #pragma unroll
-        for (int pt = 0; pt < 2; ++pt) {
+        for (int pt = 0; pt < PT; ++pt) {
             float s = 0.f;
 #pragma unroll
             for (int ot = 0; ot < 4; ++ot)
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
         }
         if (lane < 16) {
 #pragma unroll
-            for (int pt = 0; pt < 2; ++pt) {
+            for (int pt = 0; pt < PT; ++pt) {
                 const int64_t i = base + pt * 16 + lane;
                 if (i < M) {
                     const float lg = part[pt] + L.b[3 * kMlpWidth];
@@ -533,7 +539,7 @@ hipError_t launch_mlp_forward(const uint16_t *wb, const float *wf, const float *
                               float *out, uint16_t *saveF, uint16_t *saveH, hipStream_t st)
 {
     if (M <= 0) return hipSuccess;
-    int64_t tiles = (M + kPtsPerWave - 1) / kPtsPerWave;
+    int64_t tiles = (M + kFwdPts - 1) / kFwdPts;
     int64_t blocks = (tiles + kMlpWaves - 1) / kMlpWaves;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(kMlpThreads), 0, st, wb, wf,
