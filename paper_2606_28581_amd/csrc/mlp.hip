@@ -82,19 +82,24 @@ __device__ __forceinline__ void feature_chunk(const float ph[3], float cphi, flo
                                               float sth, float cth, int ks, int g, Frag &out)
 {
     if (ks < 3) {
-        const float x0 = ph[ks];
+        // frequency 4 g from the hardware sine and cosine: x = x0 2^(4g) is exact (a
+        // power-of-two scaling), r = x - 2 rint(x / 2) in [-1, 1] too, and their argument
+        // is in revolutions (r / 2, exact); frequencies 4 g + 1 .. 4 g + 3 by the double
+        // angle, sin 2a = 2 sin a cos a, cos 2a = 1 - 2 sin^2 a, which grows the error at
+        // most eightfold, still far below the BF16 rounding that follows
+        const float x = ph[ks] * (float)(1u << (4 * g));
+        const float r = x - 2.f * rintf(0.5f * x);
+        float s = __builtin_amdgcn_sinf(0.5f * r);
+        float c = __builtin_amdgcn_cosf(0.5f * r);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int k = 4 * g + q;                       // frequency
-            const float x = x0 * (float)(1u << k);        // exact: power-of-two scaling
-            const float r = x - 2.f * rintf(0.5f * x);    // exact reduction to [-1, 1]
-            // sin(pi r), cos(pi r) with the hardware sine and cosine, whose argument is in
-            // revolutions (r / 2, exact); their error is far below the BF16 rounding that
-            // follows
-            const float s = __builtin_amdgcn_sinf(0.5f * r);
-            const float c = __builtin_amdgcn_cosf(0.5f * r);
             out.h[2 * q] = f2bf(s);
             out.h[2 * q + 1] = f2bf(c);
+            if (q < 3) {
+                const float s2 = 2.f * s * c;
+                c = __fmaf_rn(-2.f * s, s, 1.f);
+                s = s2;
+            }
         }
     } else {
 #pragma unroll
