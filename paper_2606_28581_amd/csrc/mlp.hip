@@ -124,7 +124,6 @@ struct MlpLds {
     u16 W1[kMlpWidth * kMlpIn];
     u16 W2[kMlpWidth * kMlpWidth];   // columns permuted (see above)
     u16 W3[kMlpWidth * kMlpWidth];
-    float w4[kMlpWidth];
     float b[3 * kMlpWidth + 1];
 };
 
@@ -147,8 +146,6 @@ __device__ __forceinline__ void load_weights(MlpLds &L, const u16 *wb, const flo
         L.W2[i] = w2[j];
         L.W3[i] = w3[j];
     }
-    for (int i = threadIdx.x; i < kMlpWidth; i += blockDim.x)
-        L.w4[i] = bf2f(wb[kMlpW1 + kMlpW2 + kMlpW3 + i]);
     for (int i = threadIdx.x; i < 3 * kMlpWidth + 1; i += blockDim.x) L.b[i] = wf[i];
 }
 
@@ -250,6 +247,16 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr int PT = kFwdPT;
     const int64_t ntile = (M + kFwdPts - 1) / kFwdPts;
+    // output weights as an MFMA weight operand: row 0 (lanes n % 16 == 0) holds w4 in the
+    // hidden layers' input numbering, rows 1..15 are zero
+    Frag a4[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            a4[ks].h[e] = (lane & 15) == 0
+                              ? wb[kMlpW1 + kMlpW2 + kMlpW3 + hidden_input(32 * ks + 8 * (lane >> 4) + e)]
+                              : (u16)0;
     for (int64_t tile = (int64_t)blockIdx.x * kMlpWaves + wave; tile < ntile;
          tile += (int64_t)gridDim.x * kMlpWaves) {
         // weight fragments are read from LDS per tile (held across tiles they would take
@@ -299,21 +306,15 @@ __global__ __launch_bounds__(kMlpThreads) __attribute__((amdgpu_waves_per_eu(3))
         layer_t<2>(L.W3, kMlpWidth, L.b + 2 * kMlpWidth, h, lane, acc);
         relu_to_operand(acc, h);
         if (saveH) save_layer(h, saveH + 2 * M * kMlpWidth, base, M, lane);
-        // ---- output: logit = w4 . h3 + b4 (FP32); lane (q, n) holds neurons
-        // 16 ot + 4 q + 0..3 of point n, so the 4 lane groups of a column are summed
+        // ---- output: logit = w4 . h3 + b4, one more transposed MFMA layer whose weight
+        // operand holds w4 in row 0: lane n < 16 gets point n's logit in element 0
         float part[PT];
 #pragma unroll
         for (int pt = 0; pt < PT; ++pt) {
-            float s = 0.f;
-#pragma unroll
-            for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    s = __fmaf_rn(L.w4[ot * 16 + 4 * (lane >> 4) + r],
-                                  bf2f(h[pt][ot >> 1].h[4 * (ot & 1) + r]), s);
-            s += __shfl_xor(s, 16, 64);
-            s += __shfl_xor(s, 32, 64);
-            part[pt] = s;
+            f32x4 o = {0.f, 0.f, 0.f, 0.f};
+            o = mfma(a4[0], h[pt][0], o);
+            o = mfma(a4[1], h[pt][1], o);
+            part[pt] = o[0];
         }
         if (lane < 16) {
 #pragma unroll
