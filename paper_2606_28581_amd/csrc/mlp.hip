@@ -190,12 +190,19 @@ __device__ __forceinline__ void layer_t(const u16 *W, int ldw, const float *bias
     }
 }
 
-// ReLU + bf16 of a layer's accumulators into the next layer's B operands.  The ReLU is
-// one integer max on the bit pattern (every negative float, -0 included, is a negative
-// int32 and becomes +0): a float max would add a NaN-quieting max per value.
-__device__ __forceinline__ float relu(float x)
+// ReLU + bf16 of a layer's accumulators into the next layer's B operands: two values are
+// rounded to one packed bf16 pair, then the ReLU is one packed 16-bit integer max (a
+// negative bf16, -0 included, is a negative int16 and becomes +0; rounding commutes with
+// the ReLU, so the pair is bit-identical to bf16(max(x, 0))).
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b)
 {
-    return __int_as_float(max(__float_as_int(x), 0));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const i16x2 z = {0, 0};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), z));
 }
 
 template <int PT>
@@ -204,9 +211,11 @@ __device__ __forceinline__ void relu_to_operand(const f32x4 (&acc)[4][PT], Frag 
 #pragma unroll
     for (int pt = 0; pt < PT; ++pt)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) h[pt][ks].h[e] = f2bf(relu(acc[2 * ks + (e >> 2)][pt][e & 3]));
+        for (int ks = 0; ks < 2; ++ks) {
+            const f32x4 &lo = acc[2 * ks][pt], &hi = acc[2 * ks + 1][pt];
+            h[pt][ks].q = make_uint4(relu_bf16x2(lo[0], lo[1]), relu_bf16x2(lo[2], lo[3]),
+                                     relu_bf16x2(hi[0], hi[1]), relu_bf16x2(hi[2], hi[3]));
+        }
 }
 
 // the activations of one layer for the backward, [M][64] in neuron order: 4 consecutive
